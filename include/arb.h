@@ -1,0 +1,212 @@
+/*
+ * arb.h — C ABI of the MI355X (gfx950) exact k-clique counting library, libarb.so.
+ *
+ * The library computes the hot path of arb-count / arb-count-v from Shi, Dhulipala
+ * and Shun, "Parallel Clique Counting and Peeling Algorithms" (arXiv 2002.10047):
+ *   1. orient an undirected simple graph by peeling low-degree vertices in rounds
+ *      (Sec. 3.1; appendix Alg. 4 with the threshold (2+eps) x the average degree of
+ *      the vertices still present), then direct every edge from the earlier-peeled
+ *      endpoint to the later one (Sec. 3.1, last paragraph);
+ *   2. for every vertex, recursively intersect directed out-neighbour sets k-1 levels
+ *      deep to count k-cliques (Alg. 1), optionally per vertex (Sec. 3.2, the -v
+ *      variant), using the induced subgraph of N+(v) relabelled to local ids
+ *      (Sec. 3.4).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers to graph arrays, outputs and workspaces are DEVICE pointers owned by
+ *     the caller; the library never allocates or frees device memory (hipMalloc-free,
+ *     so every *_async call may be captured into a HIP graph).  Host pointers are
+ *     marked "host".
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.  Work
+ *     is enqueued on it in order.  Functions documented as "synchronises" wait for
+ *     the stream before returning.
+ *   - Integer return codes are ARB_* below.  On an error the outputs are unspecified;
+ *     nothing else is touched.  arb_last_error() returns the code of the most recent
+ *     failing call on the calling host thread.
+ *   - Graph layout: CSR with int64 row offsets (n+1 entries, offsets[0] = 0) and int32
+ *     column indices.  An undirected graph lists each edge in both rows (nnz = 2m);
+ *     rows sorted strictly ascending, no self-loops (the paper's simple undirected
+ *     graphs, Sec. 2).  A directed ("oriented") graph lists each edge once, every arc
+ *     i -> j has i < j, rows sorted strictly ascending.
+ *   - Counts are uint64 modulo 2^64.
+ */
+#ifndef ARB_H
+#define ARB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ARB_OK = 0,
+    ARB_EINVAL = 1,      /* bad argument: null pointer, k / eps / n / option out of range */
+    ARB_EGRAPH = 2,      /* input graph violates the layout above */
+    ARB_EWORKSPACE = 3,  /* workspace smaller than the matching *_workspace() size */
+    ARB_EHIP = 4,        /* a HIP runtime call failed */
+    ARB_ELIMIT = 5       /* an implementation limit was exceeded (see ARB_MAX_*) */
+};
+
+#define ARB_MAX_K 12            /* largest clique size the counting kernels take */
+#define ARB_MAX_LOCAL 768       /* largest candidate set held in LDS per work item */
+#define ARB_MAX_ROUNDS 64       /* peel rounds recorded in the round statistics */
+#define ARB_MAX_ROW_SORT 16384  /* longest directed row the orientation can sort */
+
+typedef struct {
+    int64_t n;                 /* vertices */
+    int64_t nnz;               /* stored entries = 2 x undirected edges */
+    const int64_t *offsets;    /* device, n+1 */
+    const int32_t *indices;    /* device, nnz */
+} arb_csr;
+
+typedef struct {
+    int64_t n;                 /* vertices */
+    int64_t m;                 /* arcs = undirected edges */
+    int64_t *offsets;          /* device, n+1 */
+    int32_t *indices;          /* device, m */
+} arb_ocsr;
+
+/* ---------------------------------------------------------------- orientation */
+
+/* Bytes of workspace arb_orient needs for a graph with n vertices and nnz entries. */
+size_t arb_orient_workspace(int64_t n, int64_t nnz);
+
+/*
+ * Low out-degree orientation (Sec. 3.1, appendix Alg. 4) and directing (Sec. 3.1).
+ *
+ * Rounds r = 0, 1, ... over the vertices still present: S_r = sum of their current
+ * degrees (int64), c_r = their number, T_r = floor(((2+eps) * S_r) / c_r) evaluated in
+ * IEEE double in that order; every present vertex of degree <= T_r is removed in
+ * round r, and its degree at the start of the round is recorded; afterwards each
+ * removed vertex lowers the degree of every neighbour still present by one.  The
+ * ordering sorts vertices by (round, degree at removal, id); rank[v] is v's position.
+ * The output is the directed graph in rank space: out->offsets[rank(u)] .. lists
+ * rank(w) for every neighbour w with rank(w) > rank(u), ascending.  Since at most
+ * c_r/(2+eps) vertices exceed T_r, there are at most ceil(log_{2+eps} n) rounds.
+ *
+ *   g            undirected input (device arrays)
+ *   eps          0 <= eps <= 64
+ *   validate     nonzero: check g first (O(n + m log d)); on failure return ARB_EGRAPH.
+ *                This synchronises the stream.
+ *   out          out->n = g->n, out->m = g->nnz/2; caller allocates offsets (n+1) and
+ *                indices (m) on the device
+ *   rank         device int32[n] (original id -> rank)
+ *   round        device int32[n] (original id -> peel round), nullable
+ *   deg_at_peel  device int32[n] (original id -> degree at removal), nullable
+ *   stats        device int64[2 + ARB_MAX_ROUNDS], nullable:
+ *                [0] rounds used, [1] largest out-degree, [2 + r] = T_r
+ *   ws, ws_bytes device workspace of at least arb_orient_workspace(n, nnz) bytes
+ * Errors: ARB_EINVAL, ARB_EGRAPH (validate), ARB_EWORKSPACE, ARB_ELIMIT (n >= 2^31,
+ * a degree >= 2^26, or a directed row longer than ARB_MAX_ROW_SORT), ARB_EHIP.
+ * Without `validate` the call does not synchronise (capture-safe); the ARB_ELIMIT
+ * row-length check then only reports through stats[1].
+ */
+int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *out,
+               int32_t *rank, int32_t *round, int32_t *deg_at_peel, int64_t *stats,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* Check an undirected CSR: returns ARB_OK or ARB_EGRAPH (synchronises). */
+int arb_validate(const arb_csr *g, void *ws, size_t ws_bytes, void *stream);
+
+/* Check a directed CSR: every arc ascends, rows strictly ascending, indices in range.
+ * Returns ARB_OK or ARB_EGRAPH (synchronises).  Workspace: arb_count_workspace(). */
+int arb_check_oriented(const arb_ocsr *dg, void *ws, size_t ws_bytes, void *stream);
+
+/* out[v] = in_rank_space[rank[v]] for v < n: maps per-vertex results of the rank-space
+ * graph back to original ids. */
+int arb_permute_u64(const int32_t *rank, const uint64_t *in_rank_space, uint64_t *out,
+                    int64_t n, void *stream);
+
+/* ---------------------------------------------------------------- counting */
+
+enum {
+    ARB_SCHED_PLAIN = 0,       /* one launch per tier, one team per root, degree-descending */
+    ARB_SCHED_PERSISTENT = 1,  /* persistent teams popping a device queue, degree cost */
+    ARB_SCHED_LEARNED = 2      /* persistent, queue ordered and split by the MLP cost */
+};
+
+typedef struct {
+    int schedule;          /* ARB_SCHED_* */
+    int split_min_degree;  /* roots with d+ >= this (degree schedules) are split into one
+                              item per out-neighbour; 0 = never split */
+    float split_min_cost;  /* learned schedule: split roots whose predicted log2(1+work)
+                              is >= this; 0 = never */
+    int persist_blocks_per_cu;  /* persistent grid = 256 x this (1..8) */
+    int chunk_small;       /* items popped at once by single-wave teams (1..256) */
+    const uint16_t *mlp_weights; /* device bf16 weights for ARB_SCHED_LEARNED (8641) */
+} arb_count_opts;
+
+/* Fills opts with the defaults (persistent degree schedule). */
+void arb_count_default_opts(arb_count_opts *opts);
+
+/* Bytes of workspace arb_count / arb_count_async need (n vertices, m arcs). */
+size_t arb_count_workspace(int64_t n, int64_t m, int k);
+
+/*
+ * Exact k-clique count of the undirected graph whose orientation is dg (Alg. 1,
+ * arb-count), and optionally per-vertex counts (the -v variant, Sec. 3.2):
+ * per_vertex[x] = number of k-cliques that contain vertex x (rank space).
+ * Every k-clique is found once, from its lowest-ranked vertex: for each root v the
+ * candidate set N+(v) is relabelled 0..d-1 and its induced subgraph is kept as bit
+ * rows in LDS (Sec. 3.4); the recursion intersects those rows.
+ *
+ *   dg          directed graph; arcs must ascend (arb_check_oriented)
+ *   k           1 <= k <= ARB_MAX_K (k = 1 gives n, k = 2 gives m)
+ *   total_dev   device uint64[1], overwritten with the total
+ *   per_vertex  device uint64[n], nullable; overwritten
+ *   work_out    device uint64[n], nullable; overwritten with the per-root work measure
+ *               w(v) = sum_{u in N+(v)} d+(u) + ceil(d+(v)/32) * sum_{j=1}^{k-2} c_j(v)
+ *               where c_j(v) is the number of j-cliques in G[N+(v)]  (roots with
+ *               d+(v) < k-1 and k <= 2 get 0); forces the unsplit schedule
+ *   opts        nullable (defaults)
+ * Does not synchronise; capture-safe.  Errors: ARB_EINVAL, ARB_EWORKSPACE, ARB_ELIMIT
+ * (an item's candidate set above ARB_MAX_LOCAL; reported through arb_count only, as
+ * the async form cannot see it: it then leaves total_dev = UINT64_MAX).
+ */
+int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,
+                    uint64_t *work_out, const arb_count_opts *opts,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Synchronous arb_count_async that also checks dg first; returns the total, or 0 with
+ * arb_last_error() != ARB_OK on failure.  Synchronises the stream. */
+uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex,
+                   const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- learned schedule */
+
+#define ARB_MLP_PARAMS 8641     /* 3->64->64->64->1, ReLU, weights then bias per layer */
+
+/* Per-root features in rank space: feat[3v..3v+2] = (log2(1+d+(v)),
+ * log2(1 + sum_{u in N+(v)} d+(u)), round(v)); round_orig/rank as from arb_orient. */
+int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank,
+                 float *feat, void *stream);
+
+/* y[r] = MLP(x[r]) for rows r < rows; x float[rows][3]; weights bf16 (ARB_MLP_PARAMS,
+ * layout W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[1][64] b4[1]);
+ * act (nullable) float[rows][192] receives the three hidden pre-activations for
+ * arb_mlp_backward. FP32 accumulation. */
+int arb_mlp_forward(const uint16_t *w_bf16, const float *x, int64_t rows, float *y,
+                    float *act, void *stream);
+
+/* Gradient of L = mean_r (y[r] - t[r])^2 / 2 ... given dy[r] = dL/dy[r], accumulate
+ * dL/dparams into grad (float[ARB_MLP_PARAMS], overwritten). */
+int arb_mlp_backward(const uint16_t *w_bf16, const float *x, const float *act,
+                     const float *dy, int64_t rows, float *grad, void *stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected, beta1 0.9, beta2 0.999, eps 1e-8)
+ * on fp32 master weights w, moments m and v; writes the bf16 copy (round to nearest
+ * even).  step counts from 1. */
+int arb_adam_step(float *w, uint16_t *w_bf16, const float *grad, float *m, float *v,
+                  float lr, int step, void *stream);
+
+/* ---------------------------------------------------------------- errors */
+
+int arb_last_error(void);
+const char *arb_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARB_H */

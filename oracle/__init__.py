@@ -1,0 +1,153 @@
+"""CPU oracle for the k-clique counting path.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+may import this package.  It shares no code with the HIP library
+(``paper_2002_10047_amd``): the C part lives in ``arb_oracle.c`` and is loaded here
+with ctypes; the MLP reference is numpy float64 (``oracle.mlp``).
+
+Functions follow the paper (Shi, Dhulipala, Shun, arXiv 2002.10047):
+  validate        Sec. 2 (simple undirected graphs)
+  orient          Sec. 3.1 and Alg. 4 (peel rounds), Sec. 3.1 last paragraph (directing)
+  count           the k-clique definition of Sec. 2, via Chiba-Nishizeki (Sec. 3.4)
+  brute           the definition itself, every k-subset tested
+  degeneracy      exact degeneracy, for the out-degree bound of Sec. 3.1
+  local_cliques   c_j(v), the j-cliques of G[N+(v)] (the per-root work of Alg. 1)
+  features        the per-root scheduling features (d+, sum of d+ over N+, round)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "arb_oracle.c")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile arb_oracle.c into liboracle.so (gcc, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build(force=True)
+    lib = ctypes.CDLL(_SO)
+    P = ctypes.c_void_p
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.orc_validate.argtypes = [i64, P, P]
+    lib.orc_validate.restype = i32
+    lib.orc_orient.argtypes = [i64, P, P, dbl, P, P, P, P, P, P, i32]
+    lib.orc_orient.restype = i32
+    lib.orc_count.argtypes = [i64, P, P, i32, P, i32, i64, i64, P]
+    lib.orc_count.restype = ctypes.c_uint64
+    lib.orc_brute.argtypes = [i64, P, P, i32, P]
+    lib.orc_brute.restype = ctypes.c_uint64
+    lib.orc_degeneracy.argtypes = [i64, P, P]
+    lib.orc_degeneracy.restype = i64
+    lib.orc_local_cliques.argtypes = [i64, P, P, i32, P]
+    lib.orc_local_cliques.restype = None
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(g):
+    off = np.ascontiguousarray(g.offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(g.indices, dtype=np.int32)
+    if idx.shape[0] == 0:
+        idx = np.zeros(1, dtype=np.int32)
+    return off, idx
+
+
+def validate(g) -> int:
+    """0 if g is simple, symmetric and sorted; otherwise a nonzero reason code
+    (1 offsets, 2 range, 3 self-loop, 4 unsorted/duplicate, 5 asymmetric)."""
+    off, idx = _csr(g)
+    return int(_load().orc_validate(g.n, _ptr(off), _ptr(idx)))
+
+
+def orient(g, eps: float = 1.0, max_rounds: int = 4096):
+    """Peel orientation.  Returns dict with round, deg_at_peel, rank (int32[n]),
+    ooff (int64[n+1]), oidx (int32[m]) in rank space, thresholds (int64[rounds])."""
+    off, idx = _csr(g)
+    n = g.n
+    rnd = np.zeros(max(n, 1), np.int32)
+    dap = np.zeros(max(n, 1), np.int32)
+    rank = np.zeros(max(n, 1), np.int32)
+    ooff = np.zeros(n + 1, np.int64)
+    oidx = np.zeros(max(g.m, 1), np.int32)
+    thr = np.zeros(max_rounds, np.int64)
+    r = _load().orc_orient(n, _ptr(off), _ptr(idx), float(eps), _ptr(rnd), _ptr(dap), _ptr(rank),
+                           _ptr(ooff), _ptr(oidx), _ptr(thr), max_rounds)
+    if r < 0:
+        raise RuntimeError("orientation exceeded max_rounds")
+    return dict(round=rnd[:n], deg_at_peel=dap[:n], rank=rank[:n], ooff=ooff,
+                oidx=oidx[:g.m], thresholds=thr[:r], rounds=r)
+
+
+def count(g, k: int, per_vertex: bool = False, nthreads: int = 1, stride: int = 1, phase: int = 0):
+    """Exact number of k-cliques (uint64) and optionally per-vertex incidence counts.
+    Raises OverflowError if the total reaches 2^64."""
+    off, idx = _csr(g)
+    pv = np.zeros(max(g.n, 1), np.uint64) if per_vertex else None
+    ov = ctypes.c_int(0)
+    t = _load().orc_count(g.n, _ptr(off), _ptr(idx), int(k), _ptr(pv) if pv is not None else None,
+                          int(nthreads), int(stride), int(phase), ctypes.byref(ov))
+    if ov.value:
+        raise OverflowError("k-clique total reached 2^64")
+    if per_vertex:
+        return int(t), pv[:g.n]
+    return int(t)
+
+
+def brute(g, k: int):
+    """(total, per_vertex) by testing every k-subset; n <= 64."""
+    if g.n > 64:
+        raise ValueError("brute force needs n <= 64")
+    off, idx = _csr(g)
+    pv = np.zeros(64, np.uint64)
+    t = _load().orc_brute(g.n, _ptr(off), _ptr(idx), int(k), _ptr(pv))
+    return int(t), pv[:g.n]
+
+
+def degeneracy(g) -> int:
+    off, idx = _csr(g)
+    return int(_load().orc_degeneracy(g.n, _ptr(off), _ptr(idx)))
+
+
+def local_cliques(n: int, ooff: np.ndarray, oidx: np.ndarray, jmax: int) -> np.ndarray:
+    """uint64[n, jmax]: entry (v, j-1) = number of j-cliques in G[N+(v)] of the directed graph."""
+    ooff = np.ascontiguousarray(ooff, np.int64)
+    oidx = np.ascontiguousarray(oidx, np.int32)
+    if oidx.shape[0] == 0:
+        oidx = np.zeros(1, np.int32)
+    out = np.zeros((max(n, 1), max(jmax, 1)), np.uint64)
+    if jmax >= 1:
+        _load().orc_local_cliques(n, _ptr(ooff), _ptr(oidx), int(jmax), _ptr(out))
+    return out[:n, :jmax]
+
+
+def features(n: int, ooff: np.ndarray, oidx: np.ndarray, round_rank_space: np.ndarray) -> np.ndarray:
+    """float64[n, 3]: (d+(v), sum over u in N+(v) of d+(u), round(v)) in rank space."""
+    dplus = np.diff(np.asarray(ooff, np.int64))
+    rows = np.repeat(np.arange(n), dplus)
+    s = np.zeros(n, np.float64)
+    np.add.at(s, rows, dplus[np.asarray(oidx, np.int64)].astype(np.float64))
+    return np.stack([dplus.astype(np.float64), s, np.asarray(round_rank_space, np.float64)], axis=1)

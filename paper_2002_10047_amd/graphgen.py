@@ -1,0 +1,340 @@
+"""Seeded synthetic graph generators shared by the tests, the benchmark and the oracle checks.
+
+This module only produces inputs: simple undirected graphs in CSR form (int64 row
+offsets, int32 column indices, every row sorted ascending, both directions of each
+edge present, no self-loops, no duplicates).  It holds none of the clique-counting
+or orientation arithmetic, so neither the HIP path nor the CPU oracle depends on the
+other through it.
+
+All randomness comes from numpy's PCG64 generator seeded explicitly; the same seed
+and numpy version give the same graph byte for byte.
+
+Workload families (the shapes the paper's experiments use are social/web graphs of
+Table 1; these synthetic families stand in for them):
+
+* ``er_planted``   G(n, m) with a planted clique
+* ``rmat``         recursive-matrix (R-MAT) power-law graph
+* ``chung_lu``     Chung-Lu expected-degree power-law graph with planted dense communities
+* ``rgg``          random geometric graph on the unit torus (2-D or 3-D)
+* ``batch_mix``    a batch of graphs of uneven size mixing G(n,p), R-MAT and 2-D RGG
+* small exact families: complete, Turan, cycle, star, empty, G(n,p)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "Graph", "rng", "csr_from_pairs", "er_planted", "rmat", "chung_lu", "rgg",
+    "batch_mix", "disjoint_union", "complete", "turan", "cycle", "star", "empty",
+    "gnp", "gnm", "relabel", "config_graph",
+]
+
+
+@dataclass
+class Graph:
+    """Undirected simple graph in symmetric CSR form."""
+    n: int
+    offsets: np.ndarray   # int64[n+1]
+    indices: np.ndarray   # int32[2m]
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.indices.shape[0])
+
+    @property
+    def m(self) -> int:
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def edges(self):
+        """Each undirected edge once as (u, v) with u < v."""
+        src = np.repeat(np.arange(self.n, dtype=np.int64), self.degrees())
+        dst = self.indices.astype(np.int64)
+        keep = src < dst
+        return src[keep], dst[keep]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def csr_from_pairs(n: int, u, v, name: str = "") -> Graph:
+    """Drop self-loops and duplicate pairs, then build the symmetric sorted CSR."""
+    n = int(n)
+    u = np.asarray(u, dtype=np.int64).ravel()
+    v = np.asarray(v, dtype=np.int64).ravel()
+    keep = u != v
+    u, v = u[keep], v[keep]
+    lo = np.minimum(u, v)
+    hi = np.maximum(u, v)
+    del u, v, keep
+    key = np.unique(lo * n + hi)
+    del lo, hi
+    lo = key // n
+    hi = key - lo * n
+    del key
+    both = np.empty(2 * lo.shape[0], dtype=np.int64)
+    both[: lo.shape[0]] = lo * n + hi
+    both[lo.shape[0]:] = hi * n + lo
+    del lo, hi
+    both.sort(kind="stable")
+    src = both // n
+    indices = (both - src * n).astype(np.int32)
+    del both
+    counts = np.bincount(src, minlength=n).astype(np.int64)
+    del src
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    return Graph(n, offsets, indices, name)
+
+
+def _distinct_pairs(g: np.random.Generator, n: int, m: int):
+    """m distinct uniformly random unordered pairs {a, b}, a != b."""
+    total = n * (n - 1) // 2
+    if m > total:
+        raise ValueError("more edges than pairs")
+    chosen = np.empty(0, dtype=np.int64)
+    while chosen.shape[0] < m:
+        need = m - chosen.shape[0]
+        a = g.integers(0, n, size=2 * need + 16, dtype=np.int64)
+        b = g.integers(0, n, size=2 * need + 16, dtype=np.int64)
+        keep = a != b
+        key = np.minimum(a, b)[keep] * n + np.maximum(a, b)[keep]
+        allk = np.concatenate([chosen, key])
+        _, first = np.unique(allk, return_index=True)
+        first.sort()
+        chosen = allk[first][:m]
+    return chosen // n, chosen % n
+
+
+def gnm(n: int, m: int, seed: int, name: str = "") -> Graph:
+    g = rng(seed)
+    a, b = _distinct_pairs(g, n, m)
+    return csr_from_pairs(n, a, b, name or f"gnm(n={n},m={m},seed={seed})")
+
+
+def gnp(n: int, p: float, seed: int, name: str = "") -> Graph:
+    """Erdos-Renyi G(n, p): every pair independently with probability p."""
+    g = rng(seed)
+    total = n * (n - 1) // 2
+    m = int(g.binomial(total, p)) if total else 0
+    a, b = _distinct_pairs(g, n, m) if m else (np.empty(0, np.int64), np.empty(0, np.int64))
+    return csr_from_pairs(n, a, b, name or f"gnp(n={n},p={p},seed={seed})")
+
+
+def er_planted(n: int = 2000, m: int = 20000, clique: int = 30, seed: int = 1) -> Graph:
+    """G(n, m) plus a clique on `clique` distinct uniformly chosen vertices (union, deduped)."""
+    g = rng(seed)
+    a, b = _distinct_pairs(g, n, m)
+    members = g.choice(n, size=clique, replace=False).astype(np.int64)
+    ia, ib = np.triu_indices(clique, 1)
+    a = np.concatenate([a, members[ia]])
+    b = np.concatenate([b, members[ib]])
+    gr = csr_from_pairs(n, a, b, f"er_planted(n={n},m={m},K{clique},seed={seed})")
+    gr.planted = np.sort(members)
+    return gr
+
+
+def rmat(scale: int, nsamples: int, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         seed: int = 2, permute: bool = True, chunk: int = 1 << 23) -> Graph:
+    """R-MAT: each sample descends `scale` levels choosing a quadrant with probs a, b, c, d.
+
+    Quadrant a keeps (row, col) bits (0, 0), b gives (0, 1), c gives (1, 0), d gives (1, 1).
+    A seeded random vertex permutation is applied, then self-loops and duplicates go.
+    """
+    g = rng(seed)
+    n = 1 << scale
+    us, vs = [], []
+    left = nsamples
+    while left > 0:
+        cnt = min(chunk, left)
+        left -= cnt
+        u = np.zeros(cnt, dtype=np.int64)
+        v = np.zeros(cnt, dtype=np.int64)
+        for lvl in range(scale):
+            r = g.random(cnt)
+            bit = np.int64(1) << np.int64(scale - 1 - lvl)
+            row1 = r >= (a + b)
+            col1 = ((r >= a) & (r < a + b)) | (r >= a + b + c)
+            u |= row1.astype(np.int64) * bit
+            v |= col1.astype(np.int64) * bit
+        us.append(u)
+        vs.append(v)
+    u = np.concatenate(us)
+    v = np.concatenate(vs)
+    del us, vs
+    if permute:
+        perm = g.permutation(n).astype(np.int64)
+        u = perm[u]
+        v = perm[v]
+    return csr_from_pairs(n, u, v, f"rmat(scale={scale},samples={nsamples},seed={seed})")
+
+
+def _capped_weights(n: int, beta: float, total: float, wmax: float) -> np.ndarray:
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (beta - 1.0))
+    for _ in range(100):
+        w *= total / w.sum()
+        over = w > wmax
+        if not over.any():
+            break
+        w[over] = wmax
+    return w
+
+
+def chung_lu(n: int, beta: float, npairs: int, wmax: float, ncomm: int = 0,
+             comm_lo: int = 40, comm_hi: int = 80, comm_p: float = 0.5, seed: int = 3,
+             chunk: int = 1 << 23) -> Graph:
+    """Chung-Lu power-law graph with planted dense communities.
+
+    Weights w_i proportional to (i+1)^(-1/(beta-1)), scaled so that sum(w) = 2*npairs and
+    capped at wmax (iterated rescale).  `npairs` endpoint pairs are drawn i.i.d. with each
+    endpoint proportional to w.  Then `ncomm` disjoint communities, sizes uniform in
+    [comm_lo, comm_hi], each an internal G(s, comm_p), are added.  Ids are permuted.
+    """
+    g = rng(seed)
+    w = _capped_weights(n, beta, 2.0 * npairs, wmax)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    us, vs = [], []
+    left = npairs
+    while left > 0:
+        cnt = min(chunk, left)
+        left -= cnt
+        us.append(np.minimum(np.searchsorted(cdf, g.random(cnt), side="right"), n - 1))
+        vs.append(np.minimum(np.searchsorted(cdf, g.random(cnt), side="right"), n - 1))
+    sizes = g.integers(comm_lo, comm_hi + 1, size=ncomm)
+    pool = g.permutation(n)
+    pos = 0
+    for s in sizes:
+        mem = pool[pos:pos + s].astype(np.int64)
+        pos += s
+        ia, ib = np.triu_indices(int(s), 1)
+        keep = g.random(ia.shape[0]) < comm_p
+        us.append(mem[ia[keep]])
+        vs.append(mem[ib[keep]])
+    u = np.concatenate(us).astype(np.int64)
+    v = np.concatenate(vs).astype(np.int64)
+    del us, vs
+    perm = g.permutation(n).astype(np.int64)
+    return csr_from_pairs(n, perm[u], perm[v],
+                          f"chung_lu(n={n},beta={beta},pairs={npairs},wmax={wmax},comm={ncomm},seed={seed})")
+
+
+def rgg(n: int, dim: int, avg_deg: float, seed: int) -> Graph:
+    """Random geometric graph: n uniform points on the unit torus [0,1)^dim, edge iff distance <= r,
+    with r chosen so that the expected degree is avg_deg."""
+    from scipy.spatial import cKDTree
+    g = rng(seed)
+    pts = g.random((n, dim))
+    if dim == 2:
+        r = math.sqrt(avg_deg / (math.pi * n))
+    elif dim == 3:
+        r = (avg_deg / ((4.0 / 3.0) * math.pi * n)) ** (1.0 / 3.0)
+    else:
+        raise ValueError("dim must be 2 or 3")
+    tree = cKDTree(pts, boxsize=1.0)
+    pairs = tree.query_pairs(r, output_type="ndarray")
+    return csr_from_pairs(n, pairs[:, 0], pairs[:, 1], f"rgg(n={n},dim={dim},deg={avg_deg},seed={seed})")
+
+
+def disjoint_union(graphs):
+    """Disjoint union of graphs; returns (Graph, vertex_offsets int64[G+1])."""
+    vo = np.zeros(len(graphs) + 1, dtype=np.int64)
+    eo = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, gr in enumerate(graphs):
+        vo[i + 1] = vo[i] + gr.n
+        eo[i + 1] = eo[i] + gr.nnz
+    offs = np.empty(vo[-1] + 1, dtype=np.int64)
+    idx = np.empty(eo[-1], dtype=np.int32)
+    for i, gr in enumerate(graphs):
+        offs[vo[i]:vo[i + 1]] = gr.offsets[:-1] + eo[i]
+        idx[eo[i]:eo[i + 1]] = gr.indices.astype(np.int64) + vo[i]
+    offs[-1] = eo[-1]
+    return Graph(int(vo[-1]), offs, idx, f"union({len(graphs)})"), vo
+
+
+def batch_mix(count: int = 256, m_lo: float = 1e4, m_hi: float = 5e5, seed_base: int = 4000,
+              scale_m: float = 1.0):
+    """Batch of graphs of uneven size.  Graph g uses seed seed_base+g and type g mod 3:
+    0 -> G(n,p) with mean degree 16, 1 -> R-MAT (a,b,c)=(.57,.19,.19) with scale
+    clamp(round(log2(m/16)),12,18), 2 -> 2-D RGG on the torus with mean degree 20.
+    Target edge counts are log-uniform in [m_lo, m_hi] (times scale_m)."""
+    out = []
+    for gi in range(count):
+        g = rng(seed_base + gi)
+        mg = int(math.exp(g.uniform(math.log(m_lo), math.log(m_hi))) * scale_m)
+        t = gi % 3
+        s = seed_base + gi + 100000
+        if t == 0:
+            nv = max(mg // 8, 32)
+            out.append(gnp(nv, 16.0 / (nv - 1), s, name=f"gnp{gi}"))
+        elif t == 1:
+            sc = int(min(max(round(math.log2(max(mg, 16) / 16.0)), 12), 18))
+            gr = rmat(sc, mg, seed=s)
+            gr.name = f"rmat{gi}"
+            out.append(gr)
+        else:
+            nv = max(mg // 10, 32)
+            gr = rgg(nv, 2, 20.0, s)
+            gr.name = f"rgg{gi}"
+            out.append(gr)
+    return out
+
+
+def relabel(gr: Graph, perm: np.ndarray) -> Graph:
+    """Graph with vertex v renamed perm[v]."""
+    u, v = gr.edges()
+    perm = np.asarray(perm, dtype=np.int64)
+    return csr_from_pairs(gr.n, perm[u], perm[v], gr.name + "+relabel")
+
+
+# ---------------------------------------------------------------- small exact families
+
+def complete(n: int) -> Graph:
+    ia, ib = np.triu_indices(n, 1)
+    return csr_from_pairs(n, ia, ib, f"K{n}")
+
+
+def turan(n: int, r: int) -> Graph:
+    """Complete r-partite graph with parts as equal as possible (vertex i in part i mod r)."""
+    part = np.arange(n) % r
+    ia, ib = np.triu_indices(n, 1)
+    keep = part[ia] != part[ib]
+    return csr_from_pairs(n, ia[keep], ib[keep], f"T({n},{r})")
+
+
+def cycle(n: int) -> Graph:
+    a = np.arange(n)
+    return csr_from_pairs(n, a, (a + 1) % n, f"C{n}")
+
+
+def star(n: int) -> Graph:
+    return csr_from_pairs(n, np.zeros(n - 1, np.int64), np.arange(1, n), f"S{n}")
+
+
+def empty(n: int) -> Graph:
+    return csr_from_pairs(n, np.empty(0, np.int64), np.empty(0, np.int64), f"E{n}")
+
+
+# ---------------------------------------------------------------- named workloads
+
+def config_graph(name: str) -> Graph:
+    """The named benchmark workloads at full size.
+
+    c1: G(n=2000, m=20000) + planted K30, seed 1
+    c2: R-MAT scale 20, 2^24 samples, seed 2
+    c3: Chung-Lu n=2^22, beta=2.1, 2^26 pairs, w_max=4000, 1000 communities of 40-80 at p=0.5, seed 3
+    """
+    if name == "c1":
+        return er_planted(2000, 20000, 30, seed=1)
+    if name == "c2":
+        return rmat(20, 1 << 24, seed=2)
+    if name == "c3":
+        return chung_lu(1 << 22, 2.1, 1 << 26, 4000.0, ncomm=1000, seed=3)
+    raise KeyError(name)

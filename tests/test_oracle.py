@@ -1,0 +1,278 @@
+"""Pins of the CPU oracle against facts fixed by mathematics and by the paper, independent
+of the oracle's own code: closed forms (complete and Turan graphs), the trace formula for
+triangles, brute force over all k-subsets, identities, a hand-derived orientation, and the
+orientation's theorems (Sec. 3.1: out-degree bound, round bound)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2002_10047_amd import graphgen as gg
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def esym(sizes, k):
+    """Elementary symmetric polynomial e_k of the part sizes (k-cliques of a complete
+    multipartite graph pick k distinct parts, one vertex from each)."""
+    e = [1] + [0] * k
+    for s in sizes:
+        for j in range(k, 0, -1):
+            e[j] += e[j - 1] * s
+    return e[k]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 9, 14, 20])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_complete_graph_closed_form(orc, n, k):
+    g = gg.complete(n)
+    t, pv = orc.count(g, k, per_vertex=True)
+    assert t == math.comb(n, k)
+    assert np.all(pv == math.comb(n - 1, k - 1))
+
+
+@pytest.mark.parametrize("n,r", [(10, 2), (12, 3), (17, 4), (23, 5), (30, 7), (9, 9)])
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
+def test_turan_closed_form(orc, n, r, k):
+    g = gg.turan(n, r)
+    sizes = [len(range(i, n, r)) for i in range(r)]
+    t, pv = orc.count(g, k, per_vertex=True)
+    assert t == esym(sizes, k)
+    for v in range(n):
+        p = v % r
+        assert int(pv[v]) == esym(sizes[:p] + sizes[p + 1:], k - 1)
+
+
+@pytest.mark.parametrize("seed,n,p", [(11, 60, 0.2), (12, 200, 0.08), (13, 300, 0.3)])
+def test_triangles_trace(orc, seed, n, p):
+    g = gg.gnp(n, p, seed)
+    A = np.zeros((n, n))
+    u, v = g.edges()
+    A[u, v] = 1
+    A[v, u] = 1
+    A3 = A @ A @ A                     # exact in float64 below 2^53
+    t, pv = orc.count(g, 3, per_vertex=True)
+    assert t == int(round(np.trace(A3))) // 6
+    assert np.array_equal(pv.astype(np.int64), np.rint(np.diag(A3)).astype(np.int64) // 2)
+
+
+def test_triangles_trace_c1(orc):
+    g = gg.config_graph("c1")
+    A = np.zeros((g.n, g.n))
+    u, v = g.edges()
+    A[u, v] = 1
+    A[v, u] = 1
+    d = np.einsum("ij,ji->i", A @ A, A)
+    t, pv = orc.count(g, 3, per_vertex=True)
+    assert t == int(round(d.sum())) // 6
+    assert np.array_equal(pv.astype(np.int64), np.rint(d).astype(np.int64) // 2)
+
+
+def test_brute_force_closed_forms(orc):
+    for n in [6, 10, 13]:
+        for k in range(1, n + 1):
+            t, pv = orc.brute(gg.complete(n), k)
+            assert t == math.comb(n, k)
+            assert np.all(pv == math.comb(n - 1, k - 1))
+    assert orc.brute(gg.empty(12), 3)[0] == 0
+    assert orc.brute(gg.turan(12, 3), 4)[0] == 0
+    assert orc.brute(gg.turan(12, 3), 3)[0] == 64
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_count_matches_brute_force(orc, seed):
+    r = gg.rng(100 + seed)
+    n = int(r.integers(8, 31))
+    p = float(r.uniform(0.25, 0.8))
+    g = gg.gnp(n, p, 200 + seed)
+    for k in range(1, 9):
+        tb, pvb = orc.brute(g, k)
+        t, pv = orc.count(g, k, per_vertex=True)
+        assert t == tb, (n, p, k)
+        assert np.array_equal(pv, pvb)
+
+
+def test_planted_clique_brute_40(orc):
+    # 40 vertices: G(40, 0.3) plus a planted K12
+    g0 = gg.gnp(40, 0.3, 7)
+    u, v = g0.edges()
+    mem = np.arange(5, 17)
+    ia, ib = np.triu_indices(12, 1)
+    g = gg.csr_from_pairs(40, np.concatenate([u, mem[ia]]), np.concatenate([v, mem[ib]]))
+    for k in [4, 6, 8]:
+        tb, pvb = orc.brute(g, k)
+        t, pv = orc.count(g, k, per_vertex=True)
+        assert t == tb and np.array_equal(pv, pvb)
+        assert t >= math.comb(12, k)
+
+
+def test_identities(orc):
+    g = gg.gnp(300, 0.1, 5)
+    assert orc.count(g, 1) == g.n
+    assert orc.count(g, 2) == g.m
+    t2, pv2 = orc.count(g, 2, per_vertex=True)
+    assert np.array_equal(pv2.astype(np.int64), g.degrees())
+    for k in [3, 4, 5]:
+        t, pv = orc.count(g, k, per_vertex=True)
+        assert int(pv.sum()) == k * t
+    for n in [4, 7, 50]:
+        assert orc.count(gg.cycle(n), 3) == 0
+        assert orc.count(gg.star(n), 3) == 0
+    assert orc.count(gg.cycle(3), 3) == 1
+    assert orc.count(gg.empty(0), 3) == 0
+    assert orc.count(gg.empty(10), 2) == 0
+
+
+def test_disjoint_union_additive(orc):
+    gs = [gg.gnp(40, 0.4, 1), gg.complete(9), gg.turan(20, 4), gg.cycle(12)]
+    u, vo = gg.disjoint_union(gs)
+    for k in [3, 4, 5]:
+        t, pv = orc.count(u, k, per_vertex=True)
+        parts = [orc.count(g, k, per_vertex=True) for g in gs]
+        assert t == sum(p[0] for p in parts)
+        assert np.array_equal(pv, np.concatenate([p[1] for p in parts]))
+
+
+def test_threads_and_root_sampling(orc):
+    g = gg.config_graph("c1")
+    for k in [3, 4, 5]:
+        t1, pv1 = orc.count(g, k, per_vertex=True, nthreads=1)
+        t4, pv4 = orc.count(g, k, per_vertex=True, nthreads=4)
+        assert t1 == t4 and np.array_equal(pv1, pv4)
+        assert sum(orc.count(g, k, stride=7, phase=ph) for ph in range(7)) == t1
+
+
+def test_relabel_invariance(orc):
+    g = gg.gnp(120, 0.2, 9)
+    perm = gg.rng(3).permutation(g.n)
+    h = gg.relabel(g, perm)
+    for k in [3, 4, 5, 6]:
+        t, pv = orc.count(g, k, per_vertex=True)
+        th, pvh = orc.count(h, k, per_vertex=True)
+        assert t == th
+        assert np.array_equal(pvh[perm], pv)
+
+
+def test_c1_sanity(orc):
+    g = gg.config_graph("c1")
+    t, pv = orc.count(g, 4, per_vertex=True)
+    assert t >= math.comb(30, 4)
+    assert np.all(pv[g.planted] >= math.comb(29, 3))
+
+
+def test_validate(orc):
+    g = gg.gnp(50, 0.2, 1)
+    assert orc.validate(g) == 0
+    bad = gg.Graph(g.n, g.offsets.copy(), g.indices.copy())
+    bad.indices[0] = bad.indices[1]          # duplicate / unsorted
+    assert orc.validate(bad) == 4
+    u, v = g.edges()
+    one = gg.csr_from_pairs(g.n, u[:1], v[:1])
+    asym = gg.Graph(one.n, one.offsets.copy(), one.indices.copy())
+    row = int(np.nonzero(np.diff(asym.offsets))[0][1])
+    asym.indices = asym.indices.copy()
+    asym.indices[asym.offsets[row]] = (asym.indices[asym.offsets[row]] + 1) % g.n
+    assert orc.validate(asym) != 0
+    selfl = gg.Graph(3, np.array([0, 1, 2, 2]), np.array([0, 2, 1], np.int32))
+    assert orc.validate(selfl) == 3
+
+
+# ---------------------------------------------------------------- orientation
+
+def test_orient_hand_example(orc):
+    with open(os.path.join(GOLD, "orient_example.json")) as f:
+        gold = json.load(f)
+    e = np.array(gold["edges"])
+    g = gg.csr_from_pairs(gold["n"], e[:, 0], e[:, 1])
+    o = orc.orient(g, gold["eps"])
+    assert list(o["thresholds"]) == gold["thresholds"]
+    assert list(o["round"]) == gold["round"]
+    assert list(o["deg_at_peel"]) == gold["deg_at_peel"]
+    assert list(o["rank"]) == gold["rank"]
+    for r, row in gold["out_rows_rank_space"].items():
+        r = int(r)
+        assert list(o["oidx"][o["ooff"][r]:o["ooff"][r + 1]]) == row
+
+
+def orientation_properties(g, o, eps, degen):
+    n = g.n
+    rank, rnd, dap = o["rank"], o["round"], o["deg_at_peel"]
+    ooff, oidx = o["ooff"], o["oidx"]
+    assert np.array_equal(np.sort(rank), np.arange(n))
+    # round bound: fewer than c_r/(2+eps) vertices survive a round
+    bound = max(1, math.ceil(math.log(n) / math.log(2 + eps) - 1e-12)) if n > 1 else 1
+    assert o["rounds"] <= bound
+    # each undirected edge once, arcs ascend, rows ascending
+    assert ooff[-1] == g.m
+    rows = np.repeat(np.arange(n), np.diff(ooff))
+    assert np.all(oidx > rows)
+    assert np.all((np.diff(oidx) > 0) | (np.diff(rows) > 0))
+    inv = np.empty(n, np.int64)
+    inv[rank] = np.arange(n)
+    a = inv[rows]
+    b = inv[oidx]
+    u, v = g.edges()
+    assert np.array_equal(np.sort(np.minimum(a, b) * n + np.maximum(a, b)), np.sort(u * n + v))
+    # out-degree at most the threshold of the vertex's round, and at most its
+    # degree when it was removed
+    dplus = np.diff(ooff)[rank]
+    thr = o["thresholds"][rnd]
+    assert np.all(dplus <= thr)
+    assert np.all(dplus <= dap)
+    # average degree of any subgraph is at most 2 x degeneracy
+    if n:
+        assert dplus.max() <= 2 * (2 + eps) * degen
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.5, 1.0, 2.0])
+def test_orient_properties(orc, eps):
+    for g in [gg.gnp(500, 0.02, 3), gg.config_graph("c1"), gg.rmat(12, 40000, seed=5),
+              gg.complete(30), gg.empty(5), gg.star(40), gg.turan(40, 5)]:
+        o = orc.orient(g, eps)
+        orientation_properties(g, o, eps, orc.degeneracy(g))
+
+
+def test_degeneracy_pins(orc):
+    assert orc.degeneracy(gg.complete(12)) == 11
+    assert orc.degeneracy(gg.cycle(10)) == 2
+    assert orc.degeneracy(gg.star(10)) == 1
+    assert orc.degeneracy(gg.empty(4)) == 0
+    assert orc.degeneracy(gg.turan(12, 3)) == 8
+
+
+def test_orient_threshold_rounding(orc):
+    # threshold 3 * S / c with S = 2m: star with 7 leaves, eps = 1: S = 14, c = 8,
+    # T_0 = floor(42 / 8) = 5: the centre (degree 7) survives round 0
+    o = orc.orient(gg.star(8), 1.0)
+    assert list(o["thresholds"]) == [5, 0]
+    assert o["round"][0] == 1 and np.all(o["round"][1:] == 0)
+
+
+# ---------------------------------------------------------------- local cliques
+
+def test_local_cliques_complete(orc):
+    n = 11
+    g = gg.complete(n)
+    o = orc.orient(g, 1.0)
+    c = orc.local_cliques(n, o["ooff"], o["oidx"], 5)
+    for r in range(n):
+        for j in range(1, 6):
+            assert c[r, j - 1] == math.comb(n - 1 - r, j)
+
+
+def test_local_cliques_sum_is_total(orc):
+    for g in [gg.gnp(200, 0.15, 4), gg.config_graph("c1")]:
+        o = orc.orient(g, 1.0)
+        c = orc.local_cliques(g.n, o["ooff"], o["oidx"], 6)
+        for k in range(2, 8):
+            assert int(c[:, k - 2].sum()) == orc.count(g, k)
+
+
+def test_features_definition(orc):
+    # directed path 0->1->2 plus 0->2 (a triangle in rank space)
+    ooff = np.array([0, 2, 3, 3])
+    oidx = np.array([1, 2, 2], np.int32)
+    f = orc.features(3, ooff, oidx, np.array([0, 0, 1]))
+    assert f.tolist() == [[2, 1, 0], [1, 0, 0], [0, 0, 1]]
