@@ -136,6 +136,7 @@ typedef struct {
     int persist_blocks_per_cu;  /* persistent grid = 256 x this (1..8) */
     int chunk_small;       /* items popped at once by single-wave teams (1..256) */
     const uint16_t *mlp_weights; /* device bf16 weights for ARB_SCHED_LEARNED (8641) */
+    const float *features;       /* device float[n][3] from arb_features, ARB_SCHED_LEARNED */
 } arb_count_opts;
 
 /* Fills opts with the defaults (persistent degree schedule). */
@@ -190,10 +191,24 @@ int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *r
 int arb_mlp_forward(const uint16_t *w_bf16, const float *x, int64_t rows, float *y,
                     float *act, void *stream);
 
-/* Gradient of L = mean_r (y[r] - t[r])^2 / 2 ... given dy[r] = dL/dy[r], accumulate
- * dL/dparams into grad (float[ARB_MLP_PARAMS], overwritten). */
+/* Workspace of arb_mlp_backward for `rows` rows. */
+size_t arb_mlp_workspace(int64_t rows);
+
+/* Gradient of sum_r dy[r] * y[r] with respect to the parameters (overwrites grad,
+ * float[ARB_MLP_PARAMS]); act from arb_mlp_forward on the same x and weights.  The
+ * per-row deltas and per-256-row partial sums go to ws; partials are summed in a fixed
+ * order, so the result is deterministic. */
 int arb_mlp_backward(const uint16_t *w_bf16, const float *x, const float *act,
-                     const float *dy, int64_t rows, float *grad, void *stream);
+                     const float *dy, int64_t rows, float *grad, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Mean squared error: dy[r] = (y[r] - target[r]) / rows and, if loss != NULL,
+ * *loss = sum_r (y[r] - target[r])^2 / (2 rows) (device float). */
+int arb_mse_grad(const float *y, const float *target, int64_t rows, float *dy, float *loss,
+                 void *stream);
+
+/* fp32 -> bf16, round to nearest even. */
+int arb_to_bf16(const float *w, uint16_t *w_bf16, int64_t count, void *stream);
 
 /* One Adam step (Kingma & Ba 2015, bias-corrected, beta1 0.9, beta2 0.999, eps 1e-8)
  * on fp32 master weights w, moments m and v; writes the bf16 copy (round to nearest

@@ -1,0 +1,288 @@
+"""Thin ctypes binding of libarb.so (include/arb.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP kernels.
+PyTorch provides device memory (tensors) and the stream.  Importing this module loads
+libarb.so and raises if it is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libarb.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "arb.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2002_10047_amd.build.build() "
+                      "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+_lib = ctypes.CDLL(LIB_PATH)
+
+ARB_OK, ARB_EINVAL, ARB_EGRAPH, ARB_EWORKSPACE, ARB_EHIP, ARB_ELIMIT = range(6)
+ARB_SCHED_PLAIN, ARB_SCHED_PERSISTENT, ARB_SCHED_LEARNED = range(3)
+
+
+def _define(name):
+    m = re.search(r"#define\s+" + name + r"\s+(\d+)", open(HEADER).read()) if os.path.exists(HEADER) else None
+    return int(m.group(1)) if m else None
+
+
+ARB_MAX_K = _define("ARB_MAX_K") or 12
+ARB_MAX_LOCAL = _define("ARB_MAX_LOCAL") or 768
+ARB_MAX_ROUNDS = _define("ARB_MAX_ROUNDS") or 64
+ARB_MLP_PARAMS = _define("ARB_MLP_PARAMS") or 8641
+
+
+class ArbError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {arb_error_string(code)} (code {code})")
+
+
+class ArbCsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("indices", ctypes.c_void_p)]
+
+
+class ArbOcsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("indices", ctypes.c_void_p)]
+
+
+class ArbCountOpts(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int), ("split_min_degree", ctypes.c_int),
+                ("split_min_cost", ctypes.c_float), ("persist_blocks_per_cu", ctypes.c_int),
+                ("chunk_small", ctypes.c_int), ("mlp_weights", ctypes.c_void_p),
+                ("features", ctypes.c_void_p)]
+
+
+P, I64, I32, SZ, DBL, FLT = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t,
+                              ctypes.c_double, ctypes.c_float)
+_sigs = {
+    "arb_orient_workspace": ([I64, I64], SZ),
+    "arb_orient": ([P, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
+    "arb_validate": ([P, P, SZ, P], I32),
+    "arb_check_oriented": ([P, P, SZ, P], I32),
+    "arb_permute_u64": ([P, P, P, I64, P], I32),
+    "arb_count_default_opts": ([P], None),
+    "arb_count_workspace": ([I64, I64, I32], SZ),
+    "arb_count_async": ([P, I32, P, P, P, P, P, SZ, P], I32),
+    "arb_count": ([P, I32, P, P, P, SZ, P], ctypes.c_uint64),
+    "arb_features": ([P, P, P, P, P], I32),
+    "arb_mlp_forward": ([P, P, I64, P, P, P], I32),
+    "arb_mlp_workspace": ([I64], SZ),
+    "arb_mlp_backward": ([P, P, P, P, I64, P, P, SZ, P], I32),
+    "arb_mse_grad": ([P, P, I64, P, P, P], I32),
+    "arb_adam_step": ([P, P, P, P, P, FLT, I32, P], I32),
+    "arb_to_bf16": ([P, P, I64, P], I32),
+    "arb_last_error": ([], I32),
+    "arb_error_string": ([I32], ctypes.c_char_p),
+}
+for _n, (_a, _r) in _sigs.items():
+    _f = getattr(_lib, _n)
+    _f.argtypes = _a
+    _f.restype = _r
+
+
+def arb_error_string(code: int) -> str:
+    return _lib.arb_error_string(int(code)).decode()
+
+
+def arb_last_error() -> int:
+    return int(_lib.arb_last_error())
+
+
+def _check(rc, where):
+    if rc != ARB_OK:
+        raise ArbError(rc, where)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _ws(nbytes: int, device="cuda"):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def to_device_csr(g, device="cuda"):
+    """(offsets int64, indices int32) device tensors of a graphgen.Graph."""
+    off = torch.from_numpy(np.ascontiguousarray(g.offsets, np.int64)).to(device)
+    idx = torch.from_numpy(np.ascontiguousarray(g.indices, np.int32)).to(device)
+    return off, idx
+
+
+def u64_numpy(t: torch.Tensor) -> np.ndarray:
+    """A device int64 tensor holding uint64 bit patterns, as a host uint64 array."""
+    return t.cpu().numpy().view(np.uint64)
+
+
+# ------------------------------------------------------------------ orientation
+
+def arb_orient(offsets: torch.Tensor, indices: torch.Tensor, eps: float = 1.0, validate: bool = False,
+               stream=None):
+    """arb_orient: returns dict(ooff, oidx, rank, round, deg_at_peel, stats) device tensors."""
+    n = offsets.numel() - 1
+    nnz = indices.numel()
+    dev = offsets.device
+    g = ArbCsr(n, nnz, offsets.data_ptr(), indices.data_ptr() if nnz else 0)
+    ooff = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    oidx = torch.empty(max(nnz // 2, 1), dtype=torch.int32, device=dev)
+    out = ArbOcsr(n, nnz // 2, ooff.data_ptr(), oidx.data_ptr())
+    rank = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rnd = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    dap = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    stats = torch.empty(2 + ARB_MAX_ROUNDS, dtype=torch.int64, device=dev)
+    wsb = _lib.arb_orient_workspace(n, nnz)
+    ws = _ws(wsb, dev)
+    rc = _lib.arb_orient(ctypes.byref(g), float(eps), int(bool(validate)), ctypes.byref(out), _ptr(rank),
+                         _ptr(rnd), _ptr(dap), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "arb_orient")
+    return dict(ooff=ooff, oidx=oidx[: nnz // 2], rank=rank[:n], round=rnd[:n], deg_at_peel=dap[:n],
+                stats=stats, n=n, m=nnz // 2)
+
+
+def arb_validate(offsets, indices, stream=None) -> int:
+    n = offsets.numel() - 1
+    g = ArbCsr(n, indices.numel(), offsets.data_ptr(), indices.data_ptr() if indices.numel() else 0)
+    ws = _ws(4096, offsets.device)
+    return int(_lib.arb_validate(ctypes.byref(g), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def _ocsr(ooff, oidx):
+    n = ooff.numel() - 1
+    m = oidx.numel()
+    return ArbOcsr(n, m, ooff.data_ptr(), oidx.data_ptr() if m else 0)
+
+
+def arb_check_oriented(ooff, oidx, stream=None) -> int:
+    dg = _ocsr(ooff, oidx)
+    ws = _ws(4096, ooff.device)
+    return int(_lib.arb_check_oriented(ctypes.byref(dg), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def arb_permute_u64(rank, values, stream=None):
+    out = torch.empty_like(values)
+    _check(_lib.arb_permute_u64(_ptr(rank), _ptr(values), _ptr(out), rank.numel(), _stream(stream)),
+           "arb_permute_u64")
+    return out
+
+
+# ------------------------------------------------------------------ counting
+
+def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost=0.0,
+               persist_blocks_per_cu=8, chunk_small=16, mlp_weights=None, features=None):
+    o = ArbCountOpts()
+    _lib.arb_count_default_opts(ctypes.byref(o))
+    o.schedule = int(schedule)
+    o.split_min_degree = int(split_min_degree)
+    o.split_min_cost = float(split_min_cost)
+    o.persist_blocks_per_cu = int(persist_blocks_per_cu)
+    o.chunk_small = int(chunk_small)
+    o.mlp_weights = mlp_weights.data_ptr() if mlp_weights is not None else None
+    o.features = features.data_ptr() if features is not None else None
+    o._keep = (mlp_weights, features)
+    return o
+
+
+class CountWorkspace:
+    """Reusable device workspace for arb_count_async on one graph."""
+
+    def __init__(self, ooff, oidx, k):
+        n = ooff.numel() - 1
+        self.bytes = int(_lib.arb_count_workspace(n, oidx.numel(), int(k)))
+        self.buf = _ws(self.bytes, ooff.device)
+
+
+def arb_count_async(ooff, oidx, k, total=None, per_vertex=None, work=None, opts=None, ws=None, stream=None):
+    """Enqueue arb_count_async; returns the device total tensor (int64 holding uint64)."""
+    dg = _ocsr(ooff, oidx)
+    if ws is None:
+        ws = CountWorkspace(ooff, oidx, k)
+    if total is None:
+        total = torch.empty(1, dtype=torch.int64, device=ooff.device)
+    rc = _lib.arb_count_async(ctypes.byref(dg), int(k), _ptr(total), _ptr(per_vertex), _ptr(work),
+                              ctypes.byref(opts) if opts is not None else None, _ptr(ws.buf), ws.buf.numel(),
+                              _stream(stream))
+    _check(rc, "arb_count_async")
+    return total
+
+
+def arb_count(ooff, oidx, k, per_vertex: bool = False, opts=None, ws=None, stream=None):
+    """Synchronous arb_count: returns the total (int), or (total, per_vertex uint64 numpy)."""
+    dg = _ocsr(ooff, oidx)
+    n = ooff.numel() - 1
+    if ws is None:
+        ws = CountWorkspace(ooff, oidx, k)
+    pv = torch.empty(max(n, 1), dtype=torch.int64, device=ooff.device) if per_vertex else None
+    t = _lib.arb_count(ctypes.byref(dg), int(k), _ptr(pv), ctypes.byref(opts) if opts is not None else None,
+                       _ptr(ws.buf), ws.buf.numel(), _stream(stream))
+    err = arb_last_error()
+    _check(err, "arb_count")
+    if per_vertex:
+        return int(t), u64_numpy(pv)[:n]
+    return int(t)
+
+
+# ------------------------------------------------------------------ learned schedule
+
+def arb_features(ooff, oidx, round_orig=None, rank=None, stream=None):
+    n = ooff.numel() - 1
+    feat = torch.empty(max(n, 1) * 3, dtype=torch.float32, device=ooff.device)
+    dg = _ocsr(ooff, oidx)
+    _check(_lib.arb_features(ctypes.byref(dg), _ptr(round_orig), _ptr(rank), _ptr(feat), _stream(stream)),
+           "arb_features")
+    return feat[: 3 * n].view(n, 3)
+
+
+def arb_mlp_forward(w_bf16, x, want_act=False, stream=None):
+    rows = x.shape[0]
+    y = torch.empty(max(rows, 1), dtype=torch.float32, device=x.device)
+    act = torch.empty(max(rows, 1) * 192, dtype=torch.float32, device=x.device) if want_act else None
+    _check(_lib.arb_mlp_forward(_ptr(w_bf16), _ptr(x), rows, _ptr(y), _ptr(act), _stream(stream)),
+           "arb_mlp_forward")
+    return (y[:rows], act) if want_act else y[:rows]
+
+
+def arb_mlp_backward(w_bf16, x, act, dy, stream=None):
+    rows = x.shape[0]
+    grad = torch.empty(ARB_MLP_PARAMS, dtype=torch.float32, device=x.device)
+    ws = _ws(_lib.arb_mlp_workspace(rows), x.device)
+    _check(_lib.arb_mlp_backward(_ptr(w_bf16), _ptr(x), _ptr(act), _ptr(dy), rows, _ptr(grad), _ptr(ws),
+                                 ws.numel(), _stream(stream)), "arb_mlp_backward")
+    return grad
+
+
+def arb_mse_grad(y, target, stream=None):
+    rows = y.numel()
+    dy = torch.empty_like(y)
+    loss = torch.empty(1, dtype=torch.float32, device=y.device)
+    _check(_lib.arb_mse_grad(_ptr(y), _ptr(target), rows, _ptr(dy), _ptr(loss), _stream(stream)), "arb_mse_grad")
+    return dy, loss
+
+
+def arb_adam_step(w, w_bf16, grad, m, v, lr, step, stream=None):
+    _check(_lib.arb_adam_step(_ptr(w), _ptr(w_bf16), _ptr(grad), _ptr(m), _ptr(v), float(lr), int(step),
+                              _stream(stream)), "arb_adam_step")
+
+
+def arb_to_bf16(w, stream=None):
+    out = torch.empty(w.numel(), dtype=torch.int16, device=w.device)
+    _check(_lib.arb_to_bf16(_ptr(w), _ptr(out), w.numel(), _stream(stream)), "arb_to_bf16")
+    return out
+
+
+def exported_symbols():
+    """Function names declared in include/arb.h."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(arb_[a-z0-9_]+)\s*\(", src)))

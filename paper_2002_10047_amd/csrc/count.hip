@@ -1,0 +1,377 @@
+// Host side of the counting path: k <= 2, the directed-graph check, the work schedule
+// (root sort by tier and cost, expansion into items) and the tier launches.
+#include "count_kernels.h"
+
+namespace arb {
+
+// ------------------------------------------------------------------ small k, checks
+
+__global__ void k_count_k1(int64_t n, unsigned long long *total, unsigned long long *pv) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i == 0) *total = (unsigned long long)n;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (pv) pv[i] = 1ull;
+}
+
+__global__ void k_count_k2(int64_t n, const int64_t *off, const int32_t *idx, unsigned long long *total,
+                           unsigned long long *pv) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i == 0) *total = (unsigned long long)off[n];
+    if (!pv) return;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t s = off[i], e = off[i + 1];
+        if (e > s) atomicAdd(&pv[i], (unsigned long long)(e - s));
+        for (int64_t p = s; p < e; ++p) atomicAdd(&pv[idx[p]], 1ull);
+    }
+}
+
+__global__ void k_check_oriented(int64_t n, const int64_t *off, const int32_t *idx, int64_t m, int32_t *err) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int32_t bad = 0;
+    if (wave == 0 && lane == 0 && (off[0] != 0 || off[n] != m)) bad = 1;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        int64_t s = off[v], e = off[v + 1];
+        if (e < s || s < 0 || e > m) { bad = 1; continue; }
+        for (int64_t p = s + lane; p < e; p += 64) {
+            int32_t u = idx[p];
+            if (u <= v || u >= n) bad = 1;
+            if (p > s && idx[p - 1] >= u) bad = 1;
+        }
+    }
+    if (bad) atomicOr(err, 1);
+}
+
+__global__ void k_u64_fill(unsigned long long *p, unsigned long long v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_finish(const int32_t *err, unsigned long long *total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *err) *total = ~0ull;
+}
+
+// ------------------------------------------------------------------ schedule
+//
+// Roots are sorted by (tier, cost descending) -- heavy first, the longest-processing-
+// time rule -- then expanded into items: a whole root is one item, a split root one item
+// per out-neighbour (edge parallelism, Sec. 3.4), placed where the root sorted.  Items of
+// a split root stay in the root's tier (|S| <= d+(root)); roots too large for any tier
+// are always split and use the largest tier.
+
+constexpr uint32_t kCostMax = (1u << 28) - 1;
+constexpr int kDeadTier = 7;
+
+__device__ __forceinline__ bool root_split(int64_t d, int split_deg, const float *lcost, float split_cost, int64_t v) {
+    if (d > ARB_MAX_LOCAL) return true;
+    if (lcost) return split_cost > 0.f && lcost[v] >= split_cost;
+    return split_deg > 0 && d >= split_deg;
+}
+
+__global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *lcost, uint32_t *key, int32_t *val) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = off[v + 1] - off[v];
+        uint32_t kk;
+        if (d < k - 1) {
+            kk = ((uint32_t)kDeadTier << 28) | kCostMax;
+        } else {
+            int t = tier_of(d);
+            if (t < 0) t = kNumTiers - 1;
+            float c = lcost ? fminf(fmaxf(lcost[v], 0.f) * 4096.f, (float)kCostMax) : (float)d;
+            uint32_t cq = (uint32_t)c;
+            if (cq > kCostMax) cq = kCostMax;
+            kk = ((uint32_t)t << 28) | (kCostMax - cq);
+        }
+        key[v] = kk;
+        val[v] = (int32_t)v;
+    }
+}
+
+__global__ void k_sorted_units(int64_t n, const int64_t *off, const uint32_t *key, const int32_t *val, int split_deg,
+                               const float *lcost, float split_cost, int64_t *ucnt) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t u = 0;
+        if ((key[p] >> 28) != (uint32_t)kDeadTier) {
+            const int32_t v = val[p];
+            const int64_t d = off[v + 1] - off[v];
+            u = root_split(d, split_deg, lcost, split_cost, v) ? d : 1;
+        }
+        ucnt[p] = u;
+    }
+}
+
+__global__ void k_expand(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *val, const int64_t *uoff,
+                         int32_t *iroot, int32_t *ichild) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p = wave; p < n; p += nwaves) {
+        const int64_t b = uoff[p], c = uoff[p + 1] - b;
+        if (c == 0) continue;
+        const int32_t v = val[p];
+        if (c == 1) {      // whole root (a split root has d+ >= k-1 >= 2 items)
+            if (lane == 0) { iroot[b] = v; ichild[b] = -1; }
+            continue;
+        }
+        const int64_t s = off[v];
+        for (int64_t i = lane; i < c; i += 64) {
+            iroot[b + i] = v;
+            ichild[b + i] = idx[s + i];
+        }
+    }
+}
+
+// seg[t] = first item of tier t (t = 0..8); items of dead roots are none.
+__global__ void k_segments(int64_t n, const uint32_t *key, const int64_t *uoff, int64_t *seg) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(key[p] >> 28);
+        const int tp = p > 0 ? (int)(key[p - 1] >> 28) : -1;
+        for (int tt = tp + 1; tt <= t; ++tt) seg[tt] = uoff[p];
+        if (p == n - 1)
+            for (int tt = t + 1; tt <= 8; ++tt) seg[tt] = uoff[n];
+    }
+}
+
+struct CountWs {
+    int64_t *ucnt;        // n+1, scanned in place
+    int64_t *seg;         // 16
+    int *heads;           // 16
+    int32_t *err;         // 4
+    uint32_t *key, *key_alt;
+    int32_t *val, *val_alt;
+    int32_t *iroot, *ichild;
+    float *lcost;         // n
+    unsigned long long *tot;  // total of the synchronous arb_count
+    void *scan_ws, *radix_ws;
+};
+
+static size_t carve_count(Carver &c, int64_t n, int64_t m, CountWs *w) {
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t U = nn + (m > 0 ? m : 1);
+    w->ucnt = c.take<int64_t>(nn + 1);
+    w->seg = c.take<int64_t>(16);
+    w->heads = c.take<int>(16);
+    w->err = c.take<int32_t>(4);
+    w->key = c.take<uint32_t>(nn);
+    w->key_alt = c.take<uint32_t>(nn);
+    w->val = c.take<int32_t>(nn);
+    w->val_alt = c.take<int32_t>(nn);
+    w->iroot = c.take<int32_t>(U);
+    w->ichild = c.take<int32_t>(U);
+    w->lcost = c.take<float>(nn);
+    w->tot = c.take<unsigned long long>(4);
+    w->scan_ws = c.take<char>(scan_workspace(nn + 1));
+    w->radix_ws = c.take<char>(radix_workspace(nn));
+    return c.used;
+}
+
+// learned cost (mlp.hip): predicted log2(1 + work) per root
+int learned_cost(const arb_ocsr *dg, const uint16_t *w, const float *feat, float *cost, hipStream_t s);
+
+static int launch_count(int depth, int tier, bool pv, bool instr, const CountArgs &a, unsigned grid, hipStream_t s) {
+    switch (depth < 1 ? 1 : depth) {
+        case 1: return launch_count_depth1(tier, pv, instr, a, grid, s);
+        case 2: return launch_count_depth2(tier, pv, instr, a, grid, s);
+        case 3: return launch_count_depth3(tier, pv, instr, a, grid, s);
+        case 4: return launch_count_depth4(tier, pv, instr, a, grid, s);
+        case 5: return launch_count_depth5(tier, pv, instr, a, grid, s);
+        case 6: return launch_count_depth6(tier, pv, instr, a, grid, s);
+        case 7: return launch_count_depth7(tier, pv, instr, a, grid, s);
+        case 8: return launch_count_depth8(tier, pv, instr, a, grid, s);
+        case 9: return launch_count_depth9(tier, pv, instr, a, grid, s);
+    }
+    return ARB_EINVAL;
+}
+
+static int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 256;
+        cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+    }
+    return cus;
+}
+
+}  // namespace arb
+
+using namespace arb;
+
+extern "C" void arb_count_default_opts(arb_count_opts *o) {
+    if (!o) return;
+    o->schedule = ARB_SCHED_PERSISTENT;
+    o->split_min_degree = 0;
+    o->split_min_cost = 0.f;
+    o->persist_blocks_per_cu = 8;
+    o->chunk_small = 16;
+    o->mlp_weights = nullptr;
+    o->features = nullptr;
+}
+
+extern "C" size_t arb_count_workspace(int64_t n, int64_t m, int k) {
+    (void)k;
+    Carver c(nullptr);
+    CountWs w;
+    return carve_count(c, n, m, &w) + 256;
+}
+
+static bool ocsr_ok(const arb_ocsr *dg) {
+    return dg && dg->n >= 0 && dg->m >= 0 && dg->n < (int64_t(1) << 31) && dg->offsets &&
+           (dg->m == 0 || dg->indices);
+}
+
+extern "C" int arb_check_oriented(const arb_ocsr *dg, void *ws, size_t ws_bytes, void *stream) {
+    hipStream_t s = as_stream(stream);
+    int rc = ARB_OK;
+    if (!ocsr_ok(dg) || !ws) rc = ARB_EINVAL;
+    else if (ws_bytes < 1024) rc = ARB_EWORKSPACE;
+    if (rc) { set_error(rc); return rc; }
+    int32_t *err = static_cast<int32_t *>(ws);
+    if ((rc = fill_i32(err, 0, 1, s))) { set_error(rc); return rc; }
+    k_check_oriented<<<grid_for(dg->n * 64 + 64, 256, 8192), 256, 0, s>>>(dg->n, dg->offsets, dg->indices, dg->m, err);
+    int32_t h = 0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error(ARB_EHIP);
+        return ARB_EHIP;
+    }
+    rc = h ? ARB_EGRAPH : ARB_OK;
+    set_error(rc);
+    return rc;
+}
+
+static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *work_out,
+                      const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s) {
+    if (!ocsr_ok(dg) || !total_dev || !ws) return ARB_EINVAL;
+    if (k < 1 || k > ARB_MAX_K) return ARB_EINVAL;
+    arb_count_opts opts;
+    arb_count_default_opts(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.schedule < 0 || opts.schedule > 2) return ARB_EINVAL;
+    if (opts.schedule == ARB_SCHED_LEARNED && (!opts.mlp_weights || !opts.features)) return ARB_EINVAL;
+    if (opts.persist_blocks_per_cu < 1 || opts.persist_blocks_per_cu > 8) return ARB_EINVAL;
+    if (opts.chunk_small < 1 || opts.chunk_small > 256) return ARB_EINVAL;
+    if (opts.split_min_degree < 0 || !(opts.split_min_cost >= 0.f)) return ARB_EINVAL;
+    const int64_t n = dg->n, m = dg->m;
+    if (ws_bytes < arb_count_workspace(n, m, k)) return ARB_EWORKSPACE;
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(total_dev);
+    unsigned long long *pv = reinterpret_cast<unsigned long long *>(per_vertex);
+    unsigned long long *work = reinterpret_cast<unsigned long long *>(work_out);
+    int rc;
+    const unsigned gb = grid_for(n, 256, 4096);
+    if (pv) { k_u64_fill<<<gb, 256, 0, s>>>(pv, 0ull, n); ARB_CHECK_LAUNCH(); }
+    if (work) { k_u64_fill<<<gb, 256, 0, s>>>(work, 0ull, n); ARB_CHECK_LAUNCH(); }
+    if (k == 1) { k_count_k1<<<gb, 256, 0, s>>>(n, total, pv); ARB_CHECK_LAUNCH(); return ARB_OK; }
+    if (k == 2) { k_count_k2<<<gb, 256, 0, s>>>(n, dg->offsets, dg->indices, total, pv); ARB_CHECK_LAUNCH(); return ARB_OK; }
+    k_u64_fill<<<1, 64, 0, s>>>(total, 0ull, 1);
+    ARB_CHECK_LAUNCH();
+    if (n == 0) return ARB_OK;
+
+    Carver cv(ws);
+    CountWs w;
+    carve_count(cv, n, m, &w);
+    if ((rc = fill_i32(w.err, 0, 4, s))) return rc;
+    if ((rc = fill_i32(w.heads, 0, 16, s))) return rc;
+    if ((rc = fill_i64(w.seg, 0, 16, s))) return rc;
+
+    const bool learned = opts.schedule == ARB_SCHED_LEARNED && !work;
+    const float *lcost = nullptr;
+    if (learned) {
+        if ((rc = learned_cost(dg, opts.mlp_weights, opts.features, w.lcost, s))) return rc;
+        lcost = w.lcost;
+    }
+    const int split_deg = work ? 0 : opts.split_min_degree;
+    const float split_cost = work ? 0.f : opts.split_min_cost;
+    k_root_keys<<<gb, 256, 0, s>>>(n, dg->offsets, k, lcost, w.key, w.val);
+    ARB_CHECK_LAUNCH();
+    if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, n, 31, w.radix_ws, s))) return rc;
+    k_sorted_units<<<gb, 256, 0, s>>>(n, dg->offsets, w.key, w.val, split_deg, lcost, split_cost, w.ucnt);
+    ARB_CHECK_LAUNCH();
+    if ((rc = exclusive_scan_i64(w.ucnt, w.ucnt, n, w.scan_ws, s))) return rc;
+    k_expand<<<grid_for(n * 64, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, w.val, w.ucnt, w.iroot, w.ichild);
+    ARB_CHECK_LAUNCH();
+    k_segments<<<gb, 256, 0, s>>>(n, w.key, w.ucnt, w.seg);
+    ARB_CHECK_LAUNCH();
+
+    const bool pvm = pv != nullptr;
+    const bool instr = work != nullptr;
+    int64_t hseg[16] = {0};
+    const bool plain = opts.schedule == ARB_SCHED_PLAIN;
+    if (plain) {
+        ARB_HIP(hipMemcpyAsync(hseg, w.seg, sizeof(int64_t) * 9, hipMemcpyDeviceToHost, s));
+        ARB_HIP(hipStreamSynchronize(s));
+    }
+    const int cus = device_cus();
+    for (int t = kNumTiers - 1; t >= 0; --t) {
+        CountArgs a;
+        a.off = dg->offsets;
+        a.idx = dg->indices;
+        a.n = n;
+        a.k = k;
+        a.item_root = w.iroot;
+        a.item_child = w.ichild;
+        a.seg = w.seg + t;
+        a.head = w.heads + t;
+        a.total = total;
+        a.pv = pv;
+        a.work = work;
+        a.err = w.err;
+        a.chunk = t <= 1 ? opts.chunk_small : 1;
+        a.persistent = plain ? 0 : 1;
+        a.one_item_per_team = plain ? 1 : 0;
+        const int tpb = tier_teams_per_block(t);
+        unsigned grid;
+        if (plain) {
+            const int64_t cnt = hseg[t + 1] - hseg[t];
+            if (cnt <= 0) continue;
+            grid = (unsigned)((cnt + tpb - 1) / tpb);
+        } else {
+            const size_t lds = tier_block_lds(t, pvm);
+            int per_cu = (int)((160 * 1024) / (lds > 0 ? lds : 1));
+            if (per_cu > opts.persist_blocks_per_cu) per_cu = opts.persist_blocks_per_cu;
+            if (per_cu < 1) per_cu = 1;
+            grid = (unsigned)(cus * per_cu);
+        }
+        rc = launch_count(k - 3, t, pvm, instr, a, grid, s);
+        if (rc) return rc;
+    }
+    k_finish<<<1, 64, 0, s>>>(w.err, total);
+    ARB_CHECK_LAUNCH();
+    return ARB_OK;
+}
+
+extern "C" int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,
+                               uint64_t *work_out, const arb_count_opts *opts, void *ws, size_t ws_bytes,
+                               void *stream) {
+    int rc = count_impl(dg, k, total_dev, per_vertex, work_out, opts, ws, ws_bytes, as_stream(stream));
+    set_error(rc);
+    return rc;
+}
+
+extern "C" uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex, const arb_count_opts *opts,
+                              void *ws, size_t ws_bytes, void *stream) {
+    hipStream_t s = as_stream(stream);
+    if (!ocsr_ok(dg) || !ws) { set_error(ARB_EINVAL); return 0; }
+    if (ws_bytes < arb_count_workspace(dg->n, dg->m, k)) { set_error(ARB_EWORKSPACE); return 0; }
+    if (arb_check_oriented(dg, ws, ws_bytes, stream)) return 0;
+    Carver cv(ws);
+    CountWs w;
+    carve_count(cv, dg->n, dg->m, &w);
+    int rc = count_impl(dg, k, reinterpret_cast<uint64_t *>(w.tot), per_vertex, nullptr, opts, ws, ws_bytes, s);
+    if (rc) { set_error(rc); return 0; }
+    uint64_t h = 0;
+    if (hipMemcpyAsync(&h, w.tot, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error(ARB_EHIP);
+        return 0;
+    }
+    if (h == ~0ull) {         // k_finish: an item did not fit the largest tier
+        set_error(ARB_ELIMIT);
+        return 0;
+    }
+    set_error(ARB_OK);
+    return h;
+}

@@ -1,0 +1,435 @@
+// Low out-degree orientation on the GPU (Sec. 3.1 of Shi, Dhulipala, Shun; appendix Alg. 4
+// with the threshold (2+eps) x the average degree of the vertices still present) and
+// directing of the CSR into rank space (Sec. 3.1, last paragraph).
+//
+// Per round r (all on the device, no host round trip, so the sequence can be captured):
+//   k_peel_reduce     c_r = #present, S_r = sum of present degrees
+//   k_peel_threshold  T_r = floor(((2+eps) * S_r) / c_r) in IEEE double
+//   k_peel_mark       present v with deg <= T_r: round = r, deg_at_peel = deg (start of round)
+//   k_peel_decrement  each vertex removed in round r lowers each still-present neighbour
+// A round with c_r = 0 does nothing, so the host enqueues the proven maximum number of
+// rounds, ceil(log_{2+eps} n): every round leaves fewer than c_r/(2+eps) vertices.
+#include <math.h>
+
+#include "common.h"
+
+namespace arb {
+
+constexpr int32_t kPresent = -1;
+constexpr int kDegBits = 26;   // degree at removal packed below the round in the sort key
+
+enum : int32_t {
+    kErrOffsets = 1, kErrRange = 2, kErrSelf = 4, kErrOrder = 8, kErrAsym = 16,
+    kErrDegree = 32, kErrRowLong = 64, kErrLeft = 128
+};
+
+// ------------------------------------------------------------------ validation
+
+// One wave per vertex: offsets monotone, ids in range, no self-loop, strictly ascending
+// rows, and every entry u of row v has v in row u (binary search).
+__global__ void k_validate(int64_t n, const int64_t *off, const int32_t *idx, int64_t nnz, int32_t *err) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int32_t bad = 0;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        int64_t s = off[v], e = off[v + 1];
+        if (e < s || s < 0 || e > nnz) { bad |= kErrOffsets; continue; }
+        for (int64_t p = s + lane; p < e; p += 64) {
+            int32_t u = idx[p];
+            if (u < 0 || u >= n) { bad |= kErrRange; continue; }
+            if (u == v) bad |= kErrSelf;
+            if (p > s && idx[p - 1] >= u) bad |= kErrOrder;
+            int64_t lo = off[u], hi = off[u + 1];
+            if (hi < lo || lo < 0 || hi > nnz) { bad |= kErrOffsets; continue; }
+            while (lo < hi) {
+                int64_t mid = lo + ((hi - lo) >> 1);
+                if (idx[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= off[u + 1] || idx[lo] != v) bad |= kErrAsym;
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_check_offsets_ends(int64_t n, const int64_t *off, int64_t nnz, int32_t *err) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        if (off[0] != 0 || off[n] != nnz) atomicOr(err, (int32_t)kErrOffsets);
+}
+
+// ------------------------------------------------------------------ peel rounds
+
+__global__ void k_orient_init(int64_t n, const int64_t *off, int32_t *deg, int32_t *rnd, int32_t *err) {
+    int32_t bad = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = off[v + 1] - off[v];
+        if (d >= (int64_t(1) << kDegBits)) bad = kErrDegree;
+        deg[v] = (int32_t)d;
+        rnd[v] = kPresent;
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// rs[2r] = number present at the start of round r, rs[2r+1] = sum of their degrees.
+__global__ void k_peel_reduce(int64_t n, const int32_t *deg, const int32_t *rnd, int r, int64_t *rs) {
+    if (r > 0 && rs[2 * (r - 1)] == 0) return;          // graph already empty
+    __shared__ int64_t sc[4], ss[4];
+    int64_t c = 0, s = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (rnd[v] == kPresent) { c += 1; s += deg[v]; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        s += __shfl_down(s, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { sc[wid] = c; ss[wid] = s; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t tc = 0, ts = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { tc += sc[w]; ts += ss[w]; }
+        if (tc) {
+            atomicAdd((unsigned long long *)&rs[2 * r], (unsigned long long)tc);
+            atomicAdd((unsigned long long *)&rs[2 * r + 1], (unsigned long long)ts);
+        }
+    }
+}
+
+// thr[r] = T_r, or -1 when nothing is present.  stats[0] counts the rounds that peeled.
+__global__ void k_peel_threshold(int r, double eps, const int64_t *rs, int64_t *thr, int64_t *stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t c = rs[2 * r], S = rs[2 * r + 1];
+    if (c == 0) { thr[r] = -1; return; }
+    double num = (2.0 + eps) * (double)S;     // product, then quotient: no contraction
+    double t = num / (double)c;
+    int64_t T = (int64_t)floor(t);
+    thr[r] = T;
+    if (stats) {
+        stats[0] = r + 1;
+        if (r < ARB_MAX_ROUNDS) stats[2 + r] = T;
+    }
+}
+
+__global__ void k_peel_mark(int64_t n, const int32_t *deg, int32_t *rnd, int32_t *dap, int r, const int64_t *thr) {
+    int64_t T = thr[r];
+    if (T < 0) return;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (rnd[v] == kPresent && (int64_t)deg[v] <= T) {
+            rnd[v] = r;
+            dap[v] = deg[v];
+        }
+    }
+}
+
+// Each wave looks at 64 consecutive vertices; for every one removed in round r (ballot),
+// the whole wave walks its row and decrements neighbours still present.
+__global__ void k_peel_decrement(int64_t n, const int64_t *off, const int32_t *idx, int32_t *deg,
+                                 const int32_t *rnd, int r, const int64_t *thr) {
+    if (thr[r] < 0) return;
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+        int64_t v = base + lane;
+        bool hit = v < n && rnd[v] == r;
+        uint64_t mask = __ballot(hit);
+        while (mask) {
+            int b = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            int64_t x = base + b;
+            int64_t s = off[x], e = off[x + 1];
+            for (int64_t p = s + lane; p < e; p += 64) {
+                int32_t u = idx[p];
+                if (rnd[u] == kPresent) atomicSub(&deg[u], 1);
+            }
+        }
+    }
+}
+
+__global__ void k_count_left(int64_t n, const int32_t *rnd, int32_t *err) {
+    int32_t bad = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        if (rnd[v] == kPresent) bad = kErrLeft;
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_copy_rounds(int64_t n, const int32_t *src, int32_t *dst) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        dst[v] = src[v];
+}
+
+// ------------------------------------------------------------------ rank
+
+__global__ void k_rank_keys(int64_t n, const int32_t *rnd, const int32_t *dap, uint32_t *keys, int32_t *vals) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        keys[v] = ((uint32_t)rnd[v] << kDegBits) | (uint32_t)dap[v];
+        vals[v] = (int32_t)v;
+    }
+}
+
+__global__ void k_rank_scatter(int64_t n, const int32_t *inv, int32_t *rank) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        rank[inv[p]] = (int32_t)p;
+}
+
+// ------------------------------------------------------------------ directing
+
+// One wave per vertex: number of neighbours of higher rank, stored at the vertex's rank.
+__global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *rank,
+                            int64_t *outdeg) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        int32_t rv = rank[v];
+        int64_t c = 0;
+        for (int64_t p = off[v] + lane; p < off[v + 1]; p += 64) c += rank[idx[p]] > rv;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+        if (lane == 0) outdeg[rv] = c;
+    }
+}
+
+// One wave per vertex: write the higher-ranked neighbours' ranks into the row of the
+// vertex's rank (order of the input row; sorted afterwards).
+__global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *rank,
+                           const int64_t *ooff, int32_t *oidx) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lanes_below_mask();
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        int32_t rv = rank[v];
+        int64_t w = ooff[rv];
+        int64_t s = off[v], e = off[v + 1];
+        for (int64_t b = s; b < e; b += 64) {
+            int64_t p = b + lane;
+            int32_t ru = p < e ? rank[idx[p]] : -1;
+            bool keep = ru > rv;
+            uint64_t m = __ballot(keep);
+            if (keep) oidx[w + __popcll(m & below)] = ru;
+            w += __popcll(m);
+        }
+    }
+}
+
+// Rows of at most 64 entries: one wave per row, each lane's destination is the number of
+// smaller entries (entries are distinct).
+__global__ void k_row_sort_small(int64_t n, const int64_t *ooff, int32_t *oidx) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < n; r += nwaves) {
+        int64_t s = ooff[r];
+        int d = (int)(ooff[r + 1] - s);
+        if (d <= 1 || d > 64) continue;
+        int32_t x = lane < d ? oidx[s + lane] : 0x7fffffff;
+        int pos = 0;
+        for (int j = 0; j < d; ++j) {
+            int32_t y = __shfl(x, j, 64);
+            pos += y < x;
+        }
+        if (lane < d) oidx[s + pos] = x;
+    }
+}
+
+// Rows longer than 64: one block per row, bitonic sort in LDS (padded to a power of two).
+__global__ void k_row_sort_big(int64_t n, const int64_t *ooff, int32_t *oidx, int64_t *stats, int32_t *err) {
+    extern __shared__ int32_t buf[];
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        int64_t s = ooff[r];
+        int d = (int)min<int64_t>(ooff[r + 1] - s, 0x7fffffff);
+        if (stats && threadIdx.x == 0 && d > 0)
+            atomicMax((unsigned long long *)&stats[1], (unsigned long long)d);
+        if (d <= 64) continue;
+        if (d > ARB_MAX_ROW_SORT) {
+            if (threadIdx.x == 0) atomicOr(err, (int32_t)kErrRowLong);
+            continue;
+        }
+        int p2 = 128;
+        while (p2 < d) p2 <<= 1;
+        for (int i = threadIdx.x; i < p2; i += blockDim.x) buf[i] = i < d ? oidx[s + i] : 0x7fffffff;
+        __syncthreads();
+        for (int size = 2; size <= p2; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = threadIdx.x; i < (p2 >> 1); i += blockDim.x) {
+                    int lo = 2 * i - (i & (stride - 1));
+                    int hi = lo + stride;
+                    bool up = (lo & size) == 0;
+                    int32_t a = buf[lo], b = buf[hi];
+                    if ((a > b) == up) { buf[lo] = b; buf[hi] = a; }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < d; i += blockDim.x) oidx[s + i] = buf[i];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+static int max_rounds(int64_t n, double eps) {
+    // each round leaves fewer than c/(2+eps) vertices: c_{r+1} <= ceil(c_r/(2+eps)) - 1
+    double b = 2.0 + eps;
+    int64_t c = n;
+    int r = 0;
+    while (c > 0) {
+        double q = (double)c / b;
+        int64_t nc = (int64_t)ceil(q) - 1;
+        if (nc >= c) nc = c - 1;
+        c = nc < 0 ? 0 : nc;
+        ++r;
+    }
+    return r < 1 ? 1 : r;
+}
+
+struct OrientWs {
+    int32_t *deg, *rnd, *dap, *err;
+    uint32_t *keys, *keys_alt;
+    int32_t *vals, *vals_alt;
+    int64_t *rs, *thr, *outdeg;
+    void *scan_ws, *radix_ws;
+};
+
+static size_t carve_orient(Carver &c, int64_t n, int64_t nnz, OrientWs *w) {
+    (void)nnz;
+    int64_t nn = n > 0 ? n : 1;
+    w->deg = c.take<int32_t>(nn);
+    w->rnd = c.take<int32_t>(nn);
+    w->dap = c.take<int32_t>(nn);
+    w->err = c.take<int32_t>(4);
+    w->keys = c.take<uint32_t>(nn);
+    w->keys_alt = c.take<uint32_t>(nn);
+    w->vals = c.take<int32_t>(nn);
+    w->vals_alt = c.take<int32_t>(nn);
+    w->rs = c.take<int64_t>(2 * 128);
+    w->thr = c.take<int64_t>(128);
+    w->outdeg = c.take<int64_t>(nn + 1);
+    w->scan_ws = c.take<char>(scan_workspace(nn + 1));
+    w->radix_ws = c.take<char>(radix_workspace(nn));
+    return c.used;
+}
+
+}  // namespace arb
+
+using namespace arb;
+
+extern "C" size_t arb_orient_workspace(int64_t n, int64_t nnz) {
+    Carver c(nullptr);
+    OrientWs w;
+    return carve_orient(c, n, nnz, &w) + 256;
+}
+
+static int validate_impl(const arb_csr *g, int32_t *err, hipStream_t s) {
+    ARB_CHECK_LAUNCH();
+    int rc = fill_i32(err, 0, 1, s);
+    if (rc) return rc;
+    k_check_offsets_ends<<<1, 64, 0, s>>>(g->n, g->offsets, g->nnz, err);
+    ARB_CHECK_LAUNCH();
+    if (g->n > 0) {
+        k_validate<<<grid_for(g->n * 64, 256, 8192), 256, 0, s>>>(g->n, g->offsets, g->indices, g->nnz, err);
+        ARB_CHECK_LAUNCH();
+    }
+    int32_t h = 0;
+    ARB_HIP(hipMemcpyAsync(&h, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ARB_HIP(hipStreamSynchronize(s));
+    return h ? ARB_EGRAPH : ARB_OK;
+}
+
+extern "C" int arb_validate(const arb_csr *g, void *ws, size_t ws_bytes, void *stream) {
+    int rc = ARB_OK;
+    if (!g || !ws || g->n < 0 || g->nnz < 0 || (g->n > 0 && !g->offsets) || (g->nnz > 0 && !g->indices))
+        rc = ARB_EINVAL;
+    else if (ws_bytes < 512)
+        rc = ARB_EWORKSPACE;
+    else
+        rc = validate_impl(g, static_cast<int32_t *>(ws), as_stream(stream));
+    set_error(rc);
+    return rc;
+}
+
+extern "C" int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *out, int32_t *rank,
+                          int32_t *round_out, int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes,
+                          void *stream) {
+    hipStream_t s = as_stream(stream);
+    auto fail = [](int rc) { set_error(rc); return rc; };
+    if (!g || !out || !rank || !ws) return fail(ARB_EINVAL);
+    if (!(eps >= 0.0 && eps <= 64.0)) return fail(ARB_EINVAL);
+    const int64_t n = g->n, nnz = g->nnz;
+    if (n < 0 || nnz < 0 || (nnz & 1)) return fail(ARB_EINVAL);
+    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) return fail(ARB_ELIMIT);
+    if (!g->offsets || (nnz > 0 && !g->indices) || !out->offsets || (nnz > 0 && !out->indices))
+        return fail(ARB_EINVAL);
+    if (out->n != n || out->m != nnz / 2) return fail(ARB_EINVAL);
+    if (ws_bytes < arb_orient_workspace(n, nnz)) return fail(ARB_EWORKSPACE);
+
+    Carver cv(ws);
+    OrientWs w;
+    carve_orient(cv, n, nnz, &w);
+    int rc;
+    if (validate) {
+        rc = validate_impl(g, w.err, s);
+        if (rc) return fail(rc);
+    }
+    if ((rc = fill_i32(w.err, 0, 1, s))) return fail(rc);
+    if ((rc = fill_i64(w.rs, 0, 2 * 128, s))) return fail(rc);
+    if ((rc = fill_i64(w.thr, -1, 128, s))) return fail(rc);
+    if (stats && (rc = fill_i64(stats, 0, 2 + ARB_MAX_ROUNDS, s))) return fail(rc);
+    int32_t *dap = dap_out ? dap_out : w.dap;
+    int32_t *rnd = w.rnd;
+
+    const unsigned gb = grid_for(n, 256, 2048);
+    k_orient_init<<<gb, 256, 0, s>>>(n, g->offsets, w.deg, rnd, w.err);
+    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    const int R = max_rounds(n, eps);
+    if (R > 120) return fail(ARB_ELIMIT);
+    const unsigned gw = grid_for(n, 256, 4096);
+    for (int r = 0; r < R; ++r) {
+        k_peel_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, r, w.rs);
+        k_peel_threshold<<<1, 64, 0, s>>>(r, eps, w.rs, w.thr, stats);
+        k_peel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, w.thr);
+        k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, w.thr);
+    }
+    k_count_left<<<gb, 256, 0, s>>>(n, rnd, w.err);
+    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    // rank: stable sort of ids by (round, degree at removal)
+    k_rank_keys<<<gb, 256, 0, s>>>(n, rnd, dap, w.keys, w.vals);
+    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    int round_bits = 1;
+    while ((1 << round_bits) <= R) ++round_bits;
+    if (kDegBits + round_bits > 32) return fail(ARB_ELIMIT);
+    if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, kDegBits + round_bits, w.radix_ws, s)))
+        return fail(rc);
+    k_rank_scatter<<<gb, 256, 0, s>>>(n, w.vals, rank);
+    // directing
+    const unsigned gv = grid_for(n * 64, 256, 8192);
+    k_dir_count<<<gv, 256, 0, s>>>(n, g->offsets, g->indices, rank, w.outdeg);
+    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    if ((rc = exclusive_scan_i64(w.outdeg, out->offsets, n, w.scan_ws, s))) return fail(rc);
+    k_dir_fill<<<gv, 256, 0, s>>>(n, g->offsets, g->indices, rank, out->offsets, out->indices);
+    k_row_sort_small<<<gv, 256, 0, s>>>(n, out->offsets, out->indices);
+    k_row_sort_big<<<grid_for(n, 1, 4096), 256, ARB_MAX_ROW_SORT * sizeof(int32_t), s>>>(
+        n, out->offsets, out->indices, stats, w.err);
+    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    if (round_out) {
+        k_copy_rounds<<<gb, 256, 0, s>>>(n, rnd, round_out);
+        if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    }
+    if (validate) {
+        int32_t h = 0;
+        if (hipMemcpyAsync(&h, w.err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(ARB_EHIP);
+        if (h) return fail(ARB_ELIMIT);
+    }
+    return fail(ARB_OK);
+}

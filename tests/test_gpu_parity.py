@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Orientation: rank, round, degree at removal, thresholds and the directed CSR must be
+byte-identical to the oracle's.  Counting: totals and per-vertex counts must be
+bit-identical, for every schedule."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2002_10047_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def arb():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2002_10047_amd.arb as arb
+    return arb
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_orient(arb, g, eps=1.0, validate=True):
+    off, idx = arb.to_device_csr(g)
+    o = arb.arb_orient(off, idx, eps=eps, validate=validate)
+    torch.cuda.synchronize()
+    return o
+
+
+def check_orient(arb, orc, g, eps):
+    o = gpu_orient(arb, g, eps)
+    ref = orc.orient(g, eps)
+    st = o["stats"].cpu().numpy()
+    assert st[0] == ref["rounds"], (g.name, st[0], ref["rounds"])
+    assert np.array_equal(st[2:2 + ref["rounds"]], ref["thresholds"])
+    assert np.array_equal(o["round"].cpu().numpy(), ref["round"])
+    assert np.array_equal(o["deg_at_peel"].cpu().numpy(), ref["deg_at_peel"])
+    assert np.array_equal(o["rank"].cpu().numpy(), ref["rank"])
+    assert np.array_equal(o["ooff"].cpu().numpy(), ref["ooff"])
+    assert np.array_equal(o["oidx"].cpu().numpy(), ref["oidx"])
+    if g.n:
+        assert st[1] == np.diff(ref["ooff"]).max()
+    return o
+
+
+ORIENT_GRAPHS = [
+    lambda: gg.complete(33), lambda: gg.empty(7), lambda: gg.star(100), lambda: gg.cycle(50),
+    lambda: gg.turan(60, 4), lambda: gg.config_graph("c1"), lambda: gg.gnp(3000, 0.01, 3),
+    lambda: gg.rmat(14, 200000, seed=9), lambda: gg.rgg(5000, 2, 12.0, 4),
+]
+
+
+@pytest.mark.parametrize("gi", range(len(ORIENT_GRAPHS)))
+@pytest.mark.parametrize("eps", [0.0, 1.0, 0.5])
+def test_orient_parity(arb, orc, gi, eps):
+    g = ORIENT_GRAPHS[gi]()
+    say("orient", g.name, g.n, g.m, eps)
+    check_orient(arb, orc, g, eps)
+
+
+def test_orient_hand_example(arb, orc):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "orient_example.json")) as f:
+        gold = json.load(f)
+    e = np.array(gold["edges"])
+    g = gg.csr_from_pairs(gold["n"], e[:, 0], e[:, 1])
+    o = gpu_orient(arb, g, gold["eps"])
+    st = o["stats"].cpu().numpy()
+    assert list(st[2:2 + st[0]]) == gold["thresholds"]
+    assert list(o["rank"].cpu().numpy()) == gold["rank"]
+    assert list(o["deg_at_peel"].cpu().numpy()) == gold["deg_at_peel"]
+
+
+def gpu_count(arb, o, k, per_vertex=False, **opts):
+    op = arb.count_opts(**opts) if opts else None
+    r = arb.arb_count(o["ooff"], o["oidx"], k, per_vertex=per_vertex, opts=op)
+    if per_vertex:
+        t, pv_rank = r
+        pv = pv_rank[o["rank"].cpu().numpy()]   # back to original ids
+        return t, pv
+    return r
+
+
+COUNT_GRAPHS = [
+    ("K40", lambda: gg.complete(40), range(1, 9)),
+    ("T(90,6)", lambda: gg.turan(90, 6), range(1, 9)),
+    ("gnp150", lambda: gg.gnp(150, 0.5, 1), range(3, 9)),
+    ("gnp400", lambda: gg.gnp(400, 0.3, 2), range(3, 8)),
+    ("c1", lambda: gg.config_graph("c1"), range(3, 9)),
+    ("rmat14", lambda: gg.rmat(14, 200000, seed=9), range(3, 7)),
+    ("rgg2d", lambda: gg.rgg(20000, 2, 20.0, 5), range(3, 9)),
+    ("gnp1000", lambda: gg.gnp(1000, 0.4, 3), range(3, 5)),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(COUNT_GRAPHS)))
+def test_count_parity(arb, orc, ci):
+    name, mk, ks = COUNT_GRAPHS[ci]
+    g = mk()
+    o = gpu_orient(arb, g, 1.0)
+    for k in ks:
+        say("count", name, g.n, g.m, "k", k)
+        t_ref, pv_ref = orc.count(g, k, per_vertex=True, nthreads=8)
+        t = gpu_count(arb, o, k)
+        assert t == t_ref, (name, k, t, t_ref)
+        t2, pv = gpu_count(arb, o, k, per_vertex=True)
+        assert t2 == t_ref
+        assert np.array_equal(pv, pv_ref), (name, k)
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+@pytest.mark.parametrize("split", [0, 2, 40])
+def test_schedules_identical(arb, orc, sched, split):
+    g = gg.gnp(400, 0.3, 2)
+    o = gpu_orient(arb, g, 1.0)
+    for k in [3, 4, 5, 6]:
+        say("sched", sched, "split", split, "k", k)
+        t_ref, pv_ref = orc.count(g, k, per_vertex=True, nthreads=8)
+        t, pv = gpu_count(arb, o, k, per_vertex=True, schedule=sched, split_min_degree=split)
+        assert t == t_ref
+        assert np.array_equal(pv, pv_ref)
+
+
+def test_large_outdegree_split_tier(arb, orc):
+    # complete tripartite graph: degeneracy 800 > the largest tier (768), so the
+    # heaviest roots must be split into (root, child) items
+    g = gg.turan(1200, 3)
+    o = gpu_orient(arb, g, 1.0)
+    assert int(o["stats"][1]) > 768
+    for k in [3, 4]:
+        say("turan1200 k", k)
+        t, pv = gpu_count(arb, o, k, per_vertex=True)
+        assert t == (400 ** 3 if k == 3 else 0)
+        assert np.all(pv == (400 * 400 if k == 3 else 0))
+
+
+def test_edge_cases(arb, orc):
+    for g in [gg.empty(1), gg.empty(5), gg.star(2), gg.cycle(3)]:
+        o = gpu_orient(arb, g, 1.0)
+        for k in [1, 2, 3, 4]:
+            t, pv = gpu_count(arb, o, k, per_vertex=True)
+            t_ref, pv_ref = orc.count(g, k, per_vertex=True)
+            assert t == t_ref and np.array_equal(pv, pv_ref)
+    g = gg.complete(12)
+    o = gpu_orient(arb, g, 1.0)
+    assert gpu_count(arb, o, 12) == 1
+    assert gpu_count(arb, o, 11) == 12
+
+
+def test_errors(arb):
+    g = gg.gnp(50, 0.2, 1)
+    off, idx = arb.to_device_csr(g)
+    bad = idx.clone()
+    bad[0] = bad[1]
+    assert arb.arb_validate(off, bad) == arb.ARB_EGRAPH
+    with pytest.raises(arb.ArbError) as e:
+        arb.arb_orient(off, bad, validate=True)
+    assert e.value.code == arb.ARB_EGRAPH
+    with pytest.raises(arb.ArbError):
+        arb.arb_orient(off, idx, eps=-1.0)
+    o = arb.arb_orient(off, idx)
+    assert arb.arb_check_oriented(o["ooff"], o["oidx"]) == arb.ARB_OK
+    # undirected CSR as a directed one: arcs descend -> rejected
+    assert arb.arb_check_oriented(off, idx) == arb.ARB_EGRAPH
+    with pytest.raises(arb.ArbError) as e:
+        arb.arb_count(off, idx, 3)
+    assert e.value.code == arb.ARB_EGRAPH
+    with pytest.raises(arb.ArbError) as e:
+        arb.arb_count(o["ooff"], o["oidx"], arb.ARB_MAX_K + 1)
+    assert e.value.code == arb.ARB_EINVAL
