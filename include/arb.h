@@ -49,7 +49,7 @@ enum {
     ARB_ELIMIT = 5       /* an implementation limit was exceeded (see ARB_MAX_*) */
 };
 
-#define ARB_MAX_K 12            /* largest clique size the counting kernels take */
+#define ARB_MAX_K 10            /* largest clique size the counting kernels take */
 #define ARB_MAX_LOCAL 768       /* largest candidate set held in LDS per work item */
 #define ARB_MAX_ROUNDS 64       /* peel rounds recorded in the round statistics */
 #define ARB_MAX_ROW_SORT 16384  /* longest directed row the orientation can sort */
@@ -174,6 +174,16 @@ int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *pe
  * arb_last_error() != ARB_OK on failure.  Synchronises the stream. */
 uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex,
                    const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/* Per-launch timing of the counting kernels.  While enabled, every arb_count /
+ * arb_count_async call records a HIP event before and after each of its
+ * ARB_NUM_TIERS tier kernels (tier t holds items whose candidate set fits 64, 128,
+ * 256, 384, 512, 768 local vertices).  arb_profile_read waits for the last profiled
+ * call's stream and returns per tier the kernel time in ms (0 if not launched) and its
+ * number of work items (host arrays of ARB_NUM_TIERS entries).  Synchronises. */
+#define ARB_NUM_TIERS 6
+int arb_profile_enable(int on);
+int arb_profile_read(float *tier_ms, int64_t *tier_items);
 
 /* ---------------------------------------------------------------- learned schedule */
 

@@ -79,6 +79,8 @@ _sigs = {
     "arb_mse_grad": ([P, P, I64, P, P, P], I32),
     "arb_adam_step": ([P, P, P, P, P, FLT, I32, P], I32),
     "arb_to_bf16": ([P, P, I64, P], I32),
+    "arb_profile_enable": ([I32], I32),
+    "arb_profile_read": ([P, P], I32),
     "arb_last_error": ([], I32),
     "arb_error_string": ([I32], ctypes.c_char_p),
 }
@@ -231,6 +233,18 @@ def arb_count(ooff, oidx, k, per_vertex: bool = False, opts=None, ws=None, strea
     if per_vertex:
         return int(t), u64_numpy(pv)[:n]
     return int(t)
+
+
+def arb_profile_enable(on: bool = True):
+    _check(_lib.arb_profile_enable(int(bool(on))), "arb_profile_enable")
+
+
+def arb_profile_read():
+    """(tier_ms float[6], tier_items int64[6]) of the last profiled count call."""
+    ms = (ctypes.c_float * 6)()
+    items = (ctypes.c_int64 * 6)()
+    _check(_lib.arb_profile_read(ms, items), "arb_profile_read")
+    return np.array(ms[:], np.float64), np.array(items[:], np.int64)
 
 
 # ------------------------------------------------------------------ learned schedule

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libarb.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["prims.hip", "orient.hip", "count.hip", "mlp.hip", "abi.hip"] + [f"count_d{i}.hip" for i in range(1, 10)]
+SOURCES = ["prims.hip", "orient.hip", "count.hip", "mlp.hip", "abi.hip"] + [f"count_d{i}.hip" for i in range(1, 8)]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

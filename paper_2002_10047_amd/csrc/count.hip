@@ -169,6 +169,18 @@ static size_t carve_count(Carver &c, int64_t n, int64_t m, CountWs *w) {
 // learned cost (mlp.hip): predicted log2(1 + work) per root
 int learned_cost(const arb_ocsr *dg, const uint16_t *w, const float *feat, float *cost, hipStream_t s);
 
+// Optional per-tier timing: events recorded around each tier launch of the last
+// profiled call, plus the tier item ranges.
+struct Profile {
+    bool enabled = false;
+    bool created = false;
+    hipEvent_t ev[2 * kNumTiers];
+    bool launched[kNumTiers];
+    const int64_t *seg_dev = nullptr;
+    hipStream_t stream = nullptr;
+};
+static Profile g_prof;
+
 static int launch_count(int depth, int tier, bool pv, bool instr, const CountArgs &a, unsigned grid, hipStream_t s) {
     switch (depth < 1 ? 1 : depth) {
         case 1: return launch_count_depth1(tier, pv, instr, a, grid, s);
@@ -178,8 +190,6 @@ static int launch_count(int depth, int tier, bool pv, bool instr, const CountArg
         case 5: return launch_count_depth5(tier, pv, instr, a, grid, s);
         case 6: return launch_count_depth6(tier, pv, instr, a, grid, s);
         case 7: return launch_count_depth7(tier, pv, instr, a, grid, s);
-        case 8: return launch_count_depth8(tier, pv, instr, a, grid, s);
-        case 9: return launch_count_depth9(tier, pv, instr, a, grid, s);
     }
     return ARB_EINVAL;
 }
@@ -305,6 +315,16 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
         ARB_HIP(hipStreamSynchronize(s));
     }
     const int cus = device_cus();
+    const bool prof = g_prof.enabled;
+    if (prof) {
+        if (!g_prof.created) {
+            for (int e = 0; e < 2 * kNumTiers; ++e) ARB_HIP(hipEventCreate(&g_prof.ev[e]));
+            g_prof.created = true;
+        }
+        for (int t = 0; t < kNumTiers; ++t) g_prof.launched[t] = false;
+        g_prof.seg_dev = w.seg;
+        g_prof.stream = s;
+    }
     for (int t = kNumTiers - 1; t >= 0; --t) {
         CountArgs a;
         a.off = dg->offsets;
@@ -335,8 +355,13 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
             if (per_cu < 1) per_cu = 1;
             grid = (unsigned)(cus * per_cu);
         }
+        if (prof) ARB_HIP(hipEventRecord(g_prof.ev[2 * t], s));
         rc = launch_count(k - 3, t, pvm, instr, a, grid, s);
         if (rc) return rc;
+        if (prof) {
+            ARB_HIP(hipEventRecord(g_prof.ev[2 * t + 1], s));
+            g_prof.launched[t] = true;
+        }
     }
     k_finish<<<1, 64, 0, s>>>(w.err, total);
     ARB_CHECK_LAUNCH();
@@ -374,4 +399,36 @@ extern "C" uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex, c
     }
     set_error(ARB_OK);
     return h;
+}
+
+extern "C" int arb_profile_enable(int on) {
+    g_prof.enabled = on != 0;
+    set_error(ARB_OK);
+    return ARB_OK;
+}
+
+extern "C" int arb_profile_read(float *tier_ms, int64_t *tier_items) {
+    if (!tier_ms || !tier_items) { set_error(ARB_EINVAL); return ARB_EINVAL; }
+    int64_t seg[16] = {0};
+    if (g_prof.seg_dev) {
+        if (hipStreamSynchronize(g_prof.stream) != hipSuccess ||
+            hipMemcpy(seg, g_prof.seg_dev, sizeof(int64_t) * 9, hipMemcpyDeviceToHost) != hipSuccess) {
+            set_error(ARB_EHIP);
+            return ARB_EHIP;
+        }
+    }
+    for (int t = 0; t < kNumTiers; ++t) {
+        tier_ms[t] = 0.f;
+        tier_items[t] = seg[t + 1] - seg[t];
+        if (g_prof.created && g_prof.launched[t]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, g_prof.ev[2 * t], g_prof.ev[2 * t + 1]) != hipSuccess) {
+                set_error(ARB_EHIP);
+                return ARB_EHIP;
+            }
+            tier_ms[t] = ms;
+        }
+    }
+    set_error(ARB_OK);
+    return ARB_OK;
 }

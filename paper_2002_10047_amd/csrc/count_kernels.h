@@ -30,13 +30,15 @@ namespace arb {
 // ------------------------------------------------------------------ tiers
 
 // local candidate-set capacity per tier: 32 * W (W 32-bit words per bit row)
+// TW waves per team, TPB teams per block, SPAN: id-range bitmap capacity (bits) used for
+// the membership test when the members' ids span fewer than SPAN values (else a hash).
 template <int W> struct TierCfg;
-template <> struct TierCfg<2>  { static constexpr int TW = 1, TPB = 4; };
-template <> struct TierCfg<4>  { static constexpr int TW = 1, TPB = 4; };
-template <> struct TierCfg<8>  { static constexpr int TW = 4, TPB = 1; };
-template <> struct TierCfg<12> { static constexpr int TW = 8, TPB = 1; };
-template <> struct TierCfg<16> { static constexpr int TW = 8, TPB = 1; };
-template <> struct TierCfg<24> { static constexpr int TW = 8, TPB = 1; };
+template <> struct TierCfg<2>  { static constexpr int TW = 1, TPB = 4, SPAN = 0; };
+template <> struct TierCfg<4>  { static constexpr int TW = 4, TPB = 1, SPAN = 1 << 16; };
+template <> struct TierCfg<8>  { static constexpr int TW = 4, TPB = 1, SPAN = 1 << 15; };
+template <> struct TierCfg<12> { static constexpr int TW = 8, TPB = 1, SPAN = 1 << 15; };
+template <> struct TierCfg<16> { static constexpr int TW = 8, TPB = 1, SPAN = 1 << 15; };
+template <> struct TierCfg<24> { static constexpr int TW = 8, TPB = 1, SPAN = 1 << 14; };
 
 constexpr int kNumTiers = 6;
 constexpr int kTierW[kNumTiers] = {2, 4, 8, 12, 16, 24};
@@ -62,19 +64,43 @@ template <int W, bool PV>
 struct TeamLds {
     static constexpr int D = 32 * W;             // capacity of S
     static constexpr int RS = W + 1;             // row stride in words (odd: spreads banks)
-    static constexpr int HS = pow2_at_least(2 * D);
+    static constexpr int HS = pow2_at_least(D <= 128 ? 4 * D : 2 * D);
     static constexpr int HB = __builtin_ctz(HS);
     static constexpr int TW = TierCfg<W>::TW;
     static constexpr int RING = pow2_at_least(D + 64);
+    static constexpr int SPAN = TierCfg<W>::SPAN;
+    static constexpr int SW = SPAN > 0 ? SPAN / 32 : 1;
     int32_t S[D];
-    uint64_t H[HS];
+    unsigned long long H[HS];
+    uint32_t bm[SW];        // member bitmap over ids first .. first + SPAN - 1
+    uint16_t pre[SW];       // local id of the first member in each bitmap word
     uint32_t rows[D * RS];
-    uint64_t cnt[PV ? D : 1];
+    unsigned long long cnt[PV ? D : 1];
     uint32_t ring[TW][RING];
     unsigned long long red[TW];
     int d;
     int pop;
 };
+
+// Every LDS access goes through pointers in the LDS address space, so that helpers the
+// compiler keeps out of line still use DS instructions (never generic/FLAT accesses).
+template <class L> using AS3 = __attribute__((address_space(3))) L;
+
+__device__ __forceinline__ void lds_add(AS3<unsigned long long> *p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_or(AS3<uint32_t> *p, uint32_t v) {
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned long long lds_cas(AS3<unsigned long long> *p, unsigned long long expect,
+                                                      unsigned long long desired) {
+    __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return expect;
+}
+
+template <int W> struct Bits { uint32_t w[W]; };
+struct Acc { unsigned long long c, nodes; };
 
 constexpr uint64_t kEmpty = ~0ull;
 
@@ -83,26 +109,43 @@ __device__ __forceinline__ uint32_t hslot(uint32_t key, int hb) {
 }
 
 template <class L>
-__device__ __forceinline__ void hash_insert(L *T, uint32_t key, uint32_t val) {
+__device__ __forceinline__ void hash_insert(AS3<L> *T, uint32_t key, uint32_t val) {
     uint32_t s = hslot(key, L::HB);
     const uint64_t e = ((uint64_t)val << 32) | key;
     while (true) {
-        unsigned long long old = atomicCAS((unsigned long long *)&T->H[s], (unsigned long long)kEmpty,
-                                           (unsigned long long)e);
+        unsigned long long old = lds_cas(&T->H[s], (unsigned long long)kEmpty, (unsigned long long)e);
         if (old == kEmpty) return;
         s = (s + 1) & (L::HS - 1);
     }
 }
 
 template <class L>
-__device__ __forceinline__ int hash_find(const L *T, uint32_t key) {
+__device__ __forceinline__ int hash_find(const AS3<L> *T, uint32_t key) {
     uint32_t s = hslot(key, L::HB);
     while (true) {
-        uint64_t e = T->H[s];
+        unsigned long long e = T->H[s];
         if (e == kEmpty) return -1;
         if ((uint32_t)e == key) return (int)(e >> 32);
         s = (s + 1) & (L::HS - 1);
     }
+}
+
+// Local id of vertex w in S, or -1: an id-range bitmap when the members span fewer
+// than SPAN ids (bit test, then the first-member-in-word index plus a popcount),
+// otherwise the hash.
+template <class L>
+__device__ __forceinline__ int member_find(const AS3<L> *T, int32_t w, int32_t first, int32_t last, bool bmode) {
+    if ((uint32_t)(w - first) > (uint32_t)(last - first)) return -1;
+    if constexpr (L::SPAN > 0) {
+        if (bmode) {
+            const uint32_t o = (uint32_t)(w - first);
+            const uint32_t word = T->bm[o >> 5];
+            const uint32_t bit = o & 31u;
+            if (!((word >> bit) & 1u)) return -1;
+            return (int)T->pre[o >> 5] + __popc(word & ((1u << bit) - 1u));
+        }
+    }
+    return hash_find(T, (uint32_t)w);
 }
 
 // bits of word w that stand for local ids greater than z
@@ -138,7 +181,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
 
 // Sum of x over the team (every thread of the team must call it).
 template <int TW, int TPB, class Lds>
-__device__ __forceinline__ unsigned long long team_sum(Lds *T, unsigned long long x, int wv, int lane) {
+__device__ __forceinline__ unsigned long long team_sum(AS3<Lds> *T, unsigned long long x, int wv, int lane) {
     const unsigned long long s = wave_sum(x);
     team_sync<TW, TPB>();
     if (lane == 0) T->red[wv] = s;
@@ -183,81 +226,103 @@ __device__ __forceinline__ int pop_lowest(uint32_t (&R)[W]) {
     return z;
 }
 
-// Number of L-cliques (L >= 2) inside the candidate set J.  Per-vertex mode: rows are
-// symmetric adjacency, members gain their share through cnt; instrumented mode adds the
-// search-tree nodes under J to *nodes.
+// Number of L-cliques (L >= 2) inside the candidate set J (.c); in instrumented mode
+// also the search-tree nodes under J (.nodes).  Per-vertex mode: rows are symmetric
+// adjacency and members gain their share through cnt.  Levels L >= 4 stay out of line
+// to bound code size.
 template <int W, bool PV, bool INSTR, int L, class Lds>
-__device__ unsigned long long dfs(Lds *T, const uint32_t (&J)[W], unsigned long long *nodes) {
-    uint32_t R[W];
-    unsigned long long total = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) R[w] = J[w];
+__device__ Acc dfs_body(AS3<Lds> *T, Bits<W> J);
+
+template <int W, bool PV, bool INSTR, int L, class Lds>
+__device__ __forceinline__ Acc dfs(AS3<Lds> *T, Bits<W> J) {
+    return dfs_body<W, PV, INSTR, L, Lds>(T, J);
+}
+
+template <int W, bool PV, bool INSTR, int L, class Lds>
+__device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, const Bits<W> &J) {
+    Acc out{0ull, 0ull};
     if constexpr (INSTR) {
         unsigned c = 0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) c += __popc(J[w]);
-        *nodes += c;
+        for (int w = 0; w < W; ++w) c += __popc(J.w[w]);
+        out.nodes += c;
     }
+    if constexpr (L == 2 && !PV) {
+        // leaf level on upper rows: row z has no bits below z, so the AND starts at z's word
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            uint32_t bits = J.w[w];
+            while (bits) {
+                const int z = w * 32 + __ffs(bits) - 1;
+                bits &= bits - 1;
+                const AS3<uint32_t> *rz = &T->rows[z * Lds::RS];
+                unsigned c = 0;
+#pragma unroll
+                for (int v = w; v < W; ++v) c += __popc(J.w[v] & rz[v]);
+                out.c += c;
+            }
+        }
+        return out;
+    }
+    uint32_t R[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) R[w] = J.w[w];
     while (true) {
         int z = pop_lowest<W>(R);
         if (z < 0) break;
-        const uint32_t *rz = &T->rows[z * Lds::RS];
+        const AS3<uint32_t> *rz = &T->rows[z * Lds::RS];
         if constexpr (L == 2) {
-            if constexpr (PV) {
-                unsigned a = 0, c = 0;
+            unsigned a = 0, c = 0;
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    uint32_t t = J[w] & rz[w];
-                    a += __popc(t);
-                    c += __popc(t & gtmask(z, w));
-                }
-                if (a) atomicAdd((unsigned long long *)&T->cnt[z], (unsigned long long)a);
-                total += c;
-            } else {
-                unsigned c = 0;
-#pragma unroll
-                for (int w = 0; w < W; ++w) c += __popc(J[w] & rz[w]);
-                total += c;
+            for (int w = 0; w < W; ++w) {
+                uint32_t t = J.w[w] & rz[w];
+                a += __popc(t);
+                c += __popc(t & gtmask(z, w));
             }
+            if (a) lds_add(&T->cnt[z], (unsigned long long)a);
+            out.c += c;
         } else {
-            uint32_t K[W];
+            Bits<W> K;
 #pragma unroll
-            for (int w = 0; w < W; ++w) K[w] = PV ? (J[w] & rz[w] & gtmask(z, w)) : (J[w] & rz[w]);
-            unsigned long long c = dfs<W, PV, INSTR, L - 1, Lds>(T, K, nodes);
+            for (int w = 0; w < W; ++w) K.w[w] = PV ? (J.w[w] & rz[w] & gtmask(z, w)) : (J.w[w] & rz[w]);
+            Acc sub;
+            if constexpr (L - 1 <= 3) sub = dfs_inline<W, PV, INSTR, L - 1, Lds>(T, K);
+            else sub = dfs_body<W, PV, INSTR, L - 1, Lds>(T, K);
             if constexpr (PV) {
-                if (c) atomicAdd((unsigned long long *)&T->cnt[z], c);
+                if (sub.c) lds_add(&T->cnt[z], sub.c);
             }
-            total += c;
+            out.c += sub.c;
+            out.nodes += sub.nodes;
         }
     }
-    return total;
+    return out;
+}
+
+template <int W, bool PV, bool INSTR, int L, class Lds>
+__device__ __attribute__((noinline)) Acc dfs_body(AS3<Lds> *T, Bits<W> J) {
+    return dfs_inline<W, PV, INSTR, L, Lds>(T, J);
 }
 
 template <int W, int LMAX, bool PV, bool INSTR, class Lds>
-__device__ __forceinline__ unsigned long long dfs_dispatch(Lds *T, const uint32_t (&J)[W], int L,
-                                                           unsigned long long *nodes) {
-    if constexpr (LMAX >= 2) if (L == 2) return dfs<W, PV, INSTR, 2, Lds>(T, J, nodes);
-    if constexpr (LMAX >= 3) if (L == 3) return dfs<W, PV, INSTR, 3, Lds>(T, J, nodes);
-    if constexpr (LMAX >= 4) if (L == 4) return dfs<W, PV, INSTR, 4, Lds>(T, J, nodes);
-    if constexpr (LMAX >= 5) if (L == 5) return dfs<W, PV, INSTR, 5, Lds>(T, J, nodes);
-    if constexpr (LMAX >= 6) if (L == 6) return dfs<W, PV, INSTR, 6, Lds>(T, J, nodes);
-    if constexpr (LMAX >= 7) if (L == 7) return dfs<W, PV, INSTR, 7, Lds>(T, J, nodes);
-    if constexpr (LMAX >= 8) if (L == 8) return dfs<W, PV, INSTR, 8, Lds>(T, J, nodes);
-    if constexpr (LMAX >= 9) if (L == 9) return dfs<W, PV, INSTR, 9, Lds>(T, J, nodes);
-    return 0;
+__device__ __forceinline__ Acc dfs_dispatch(AS3<Lds> *T, const Bits<W> &J, int L) {
+    if constexpr (LMAX >= 2) if (L == 2) return dfs_inline<W, PV, INSTR, 2, Lds>(T, J);
+    if constexpr (LMAX >= 3) if (L == 3) return dfs_inline<W, PV, INSTR, 3, Lds>(T, J);
+    if constexpr (LMAX >= 4) if (L == 4) return dfs_body<W, PV, INSTR, 4, Lds>(T, J);
+    if constexpr (LMAX >= 5) if (L == 5) return dfs_body<W, PV, INSTR, 5, Lds>(T, J);
+    if constexpr (LMAX >= 6) if (L == 6) return dfs_body<W, PV, INSTR, 6, Lds>(T, J);
+    if constexpr (LMAX >= 7) if (L == 7) return dfs_body<W, PV, INSTR, 7, Lds>(T, J);
+    return Acc{0ull, 0ull};
 }
-static_assert(ARB_MAX_K - 3 <= 9, "dfs_dispatch covers L up to ARB_MAX_K - 3");
-constexpr int kMaxDepth = ARB_MAX_K - 3;
+static_assert(ARB_MAX_K - 3 <= 7, "dfs_dispatch covers L up to ARB_MAX_K - 3");
 
 // One pair (x, y) of the induced subgraph, x < y, both chosen: count the cliques that
-// extend it with `need` more vertices from S (need >= 1).
+// extend it with `need` more vertices from S (need >= 1); .nodes as in dfs.
 template <int W, int LMAX, bool PV, bool INSTR, class Lds>
-__device__ unsigned long long do_pair(Lds *T, uint32_t p, int need, unsigned long long *nodes) {
+__device__ __forceinline__ Acc do_pair(AS3<Lds> *T, uint32_t p, int need) {
     const int x = (int)(p >> 16), y = (int)(p & 0xffffu);
-    const uint32_t *rx = &T->rows[x * Lds::RS];
-    const uint32_t *ry = &T->rows[y * Lds::RS];
-    if constexpr (INSTR) *nodes += 1;
-    uint32_t J[W];
+    const AS3<uint32_t> *rx = &T->rows[x * Lds::RS];
+    const AS3<uint32_t> *ry = &T->rows[y * Lds::RS];
+    Acc out{0ull, INSTR ? 1ull : 0ull};
     if (need == 1 || LMAX < 2) {
         if constexpr (PV) {
             unsigned a = 0, c = 0;
@@ -267,33 +332,37 @@ __device__ unsigned long long do_pair(Lds *T, uint32_t p, int need, unsigned lon
                 a += __popc(t & gtmask(x, w));
                 c += __popc(t & gtmask(y, w));
             }
-            if (a) atomicAdd((unsigned long long *)&T->cnt[y], (unsigned long long)a);
-            if (c) atomicAdd((unsigned long long *)&T->cnt[x], (unsigned long long)c);
-            return c;
+            if (a) lds_add(&T->cnt[y], (unsigned long long)a);
+            if (c) lds_add(&T->cnt[x], (unsigned long long)c);
+            out.c = c;
         } else {
             unsigned c = 0;
 #pragma unroll
             for (int w = 0; w < W; ++w) c += __popc(rx[w] & ry[w]);
-            return c;
+            out.c = c;
         }
+        return out;
     }
+    Bits<W> J;
 #pragma unroll
-    for (int w = 0; w < W; ++w) J[w] = PV ? (rx[w] & ry[w] & gtmask(y, w)) : (rx[w] & ry[w]);
-    unsigned long long c = dfs_dispatch<W, LMAX, PV, INSTR, Lds>(T, J, need, nodes);
+    for (int w = 0; w < W; ++w) J.w[w] = PV ? (rx[w] & ry[w] & gtmask(y, w)) : (rx[w] & ry[w]);
+    const Acc sub = dfs_dispatch<W, LMAX, PV, INSTR, Lds>(T, J, need);
     if constexpr (PV) {
-        if (c) {
-            atomicAdd((unsigned long long *)&T->cnt[x], c);
-            atomicAdd((unsigned long long *)&T->cnt[y], c);
+        if (sub.c) {
+            lds_add(&T->cnt[x], sub.c);
+            lds_add(&T->cnt[y], sub.c);
         }
     }
-    return c;
+    out.c = sub.c;
+    out.nodes += sub.nodes;
+    return out;
 }
 
 // ------------------------------------------------------------------ one work item
 
 template <int W, int LMAX, bool PV, bool INSTR>
-__device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root, int32_t child,
-                             int tlid, unsigned long long *acc) {
+__device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *T, const CountArgs a, int32_t root,
+                                                             int32_t child, int tlid) {
     using Lds = TeamLds<W, PV>;
     constexpr int TW = TierCfg<W>::TW, TPB = TierCfg<W>::TPB;
     constexpr int TT = 64 * TW;
@@ -307,7 +376,7 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
         const int64_t d = a.off[root + 1] - s0;
         if (d > Lds::D) {
             if (tlid == 0) atomicOr(a.err, 1);
-            return;
+            return 0;
         }
         for (int i = tlid; i < d; i += TT) T->S[i] = a.idx[s0 + i];
         if (tlid == 0) T->d = (int)d;
@@ -346,15 +415,31 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
     }
     team_sync<TW, TPB>();
     const int d = T->d;
-    if (d < need || d == 0) return;     // no clique fits (need >= 1 here)
+    if (d < need || d == 0) return 0;   // no clique fits (need >= 1 here)
 
-    for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
+    const int32_t first = T->S[0], last = T->S[d - 1];
+    bool bmode = false;
+    if constexpr (Lds::SPAN > 0) bmode = (int64_t)last - (int64_t)first < (int64_t)Lds::SPAN;
+    if (bmode) {
+        const int nw = ((last - first) >> 5) + 1;
+        for (int i = tlid; i < nw; i += TT) T->bm[i] = 0u;
+    } else {
+        for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
+    }
     if (need >= 3)
         for (int i = tlid; i < d * Lds::RS; i += TT) T->rows[i] = 0u;
     if constexpr (PV)
         for (int i = tlid; i < d; i += TT) T->cnt[i] = 0ull;
     team_sync<TW, TPB>();
-    for (int i = tlid; i < d; i += TT) hash_insert(T, (uint32_t)T->S[i], (uint32_t)i);
+    if (bmode) {
+        for (int i = tlid; i < d; i += TT) {
+            const uint32_t o = (uint32_t)(T->S[i] - first);
+            lds_or(&T->bm[o >> 5], 1u << (o & 31u));
+            if (i == 0 || ((uint32_t)(T->S[i - 1] - first) >> 5) != (o >> 5)) T->pre[o >> 5] = (uint16_t)i;
+        }
+    } else {
+        for (int i = tlid; i < d; i += TT) hash_insert(T, (uint32_t)T->S[i], (uint32_t)i);
+    }
     team_sync<TW, TPB>();
 
     unsigned long long mine = 0;      // this lane's share of the item's clique count
@@ -366,7 +451,9 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
         if constexpr (PV)
             for (int i = tlid; i < d; i += TT) T->cnt[i] = 1ull;
     } else {
-        const int32_t maxS = T->S[d - 1];
+        // second level: read N+(u) for each member u (four 64-lane chunks in flight per
+        // wave) and keep the entries that are members; rows ascend, so a list is left as
+        // soon as it passes the largest member
         for (int i = wv; i < d; i += TW) {
             const int32_t u = T->S[i];
             const int64_t s = a.off[u], e = a.off[u + 1];
@@ -374,27 +461,33 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
                 if (lane == 0) gather += (unsigned long long)(e - s);
             }
             unsigned rowcnt = 0;
-            for (int64_t b = s; b < e; b += 64) {
-                const int64_t p = b + lane;
-                const int32_t w = p < e ? a.idx[p] : 0x7fffffff;
-                if (__shfl(w, 0, 64) > maxS) break;       // rows ascend: nothing further matches
-                const int j = w <= maxS ? hash_find(T, (uint32_t)w) : -1;
-                const bool hit = j >= 0;
-                if (need == 2) {
-                    uint64_t m = __ballot(hit);
-                    if (hit) mine += 1;
-                    rowcnt += (unsigned)__popcll(m);
-                    if constexpr (PV) {
-                        if (hit) atomicAdd((unsigned long long *)&T->cnt[j], 1ull);
-                    }
-                } else if (hit) {
-                    atomicOr(&T->rows[i * Lds::RS + (j >> 5)], 1u << (j & 31));
-                    if constexpr (PV) atomicOr(&T->rows[j * Lds::RS + (i >> 5)], 1u << (i & 31));
+            for (int64_t b = s; b < e; b += 256) {
+                int32_t wc[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int64_t p = b + 64 * c + lane;
+                    wc[c] = p < e ? a.idx[p] : 0x7fffffff;
                 }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = member_find(T, wc[c], first, last, bmode);
+                    const bool hit = j >= 0;
+                    if (need == 2) {
+                        if (hit) mine += 1;
+                        if constexpr (PV) {
+                            rowcnt += (unsigned)__popcll(__ballot(hit));
+                            if (hit) lds_add(&T->cnt[j], 1ull);
+                        }
+                    } else if (hit) {
+                        lds_or(&T->rows[i * Lds::RS + (j >> 5)], 1u << (j & 31));
+                        if constexpr (PV) lds_or(&T->rows[j * Lds::RS + (i >> 5)], 1u << (i & 31));
+                    }
+                }
+                if (__shfl(wc[3], 63, 64) > last) break;
             }
             if constexpr (PV) {
                 if (need == 2 && lane == 0 && rowcnt)
-                    atomicAdd((unsigned long long *)&T->cnt[i], (unsigned long long)rowcnt);
+                    lds_add(&T->cnt[i], (unsigned long long)rowcnt);
             }
         }
         if constexpr (INSTR) {
@@ -403,7 +496,7 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
         if (need >= 3) {
             team_sync<TW, TPB>();
             // pairs (x, y), y > x adjacent, spread over the lanes through the wave's ring
-            uint32_t *ring = T->ring[wv];
+            AS3<uint32_t> *ring = T->ring[wv];
             unsigned head = 0, tail = 0;
             const int pneed = need - 2;
             for (int x = wv; x < d; x += TW) {
@@ -432,7 +525,9 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
                 wave_fence();
                 while (tail - head >= 64) {
                     uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                    mine += do_pair<W, LMAX, PV, INSTR, Lds>(T, p, pneed, &nodes);
+                    const Acc r = do_pair<W, LMAX, PV, INSTR, Lds>(T, p, pneed);
+                    mine += r.c;
+                    nodes += r.nodes;
                     head += 64;
                 }
                 wave_fence();
@@ -440,13 +535,14 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
             if (tail != head) {
                 if (lane < (int)(tail - head)) {
                     uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                    mine += do_pair<W, LMAX, PV, INSTR, Lds>(T, p, pneed, &nodes);
+                    const Acc r = do_pair<W, LMAX, PV, INSTR, Lds>(T, p, pneed);
+                    mine += r.c;
+                    nodes += r.nodes;
                 }
             }
         }
     }
 
-    *acc += mine;
     if constexpr (PV || INSTR) {
         const unsigned long long item = team_sum<TW, TPB>(T, mine, wv, lane);
         if constexpr (PV) {
@@ -465,6 +561,7 @@ __device__ void process_item(TeamLds<W, PV> *T, const CountArgs &a, int32_t root
             if (tlid == 0 && child < 0) a.work[root] = tg + (unsigned long long)((d + 31) / 32) * tn;
         }
     }
+    return mine;
 }
 
 template <int W, int LMAX, bool PV, bool INSTR>
@@ -475,17 +572,17 @@ k_count(CountArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int team = threadIdx.x / (64 * TW);
     const int tlid = threadIdx.x % (64 * TW);
-    Lds *T = reinterpret_cast<Lds *>(smem + (size_t)team * ((sizeof(Lds) + 15) & ~size_t(15)));
+    AS3<Lds> *T = (AS3<Lds> *)(smem + (size_t)team * ((sizeof(Lds) + 15) & ~size_t(15)));
     const int64_t beg = a.seg[0], end = a.seg[1];
     unsigned long long acc = 0;
     const int64_t gteam = (int64_t)blockIdx.x * TPB + team;
     if (a.one_item_per_team) {
         int64_t it = beg + gteam;
-        if (it < end) process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid, &acc);
+        if (it < end) acc += process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid);
     } else if (!a.persistent) {
         const int64_t nteams = (int64_t)gridDim.x * TPB;
         for (int64_t it = beg + gteam; it < end; it += nteams)
-            process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid, &acc);
+            acc += process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid);
     } else {
         while (true) {
             team_sync<TW, TPB>();
@@ -495,7 +592,7 @@ k_count(CountArgs a) {
             if (first >= end) break;
             const int64_t last = min(first + (int64_t)a.chunk, end);
             for (int64_t it = first; it < last; ++it)
-                process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid, &acc);
+                acc += process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid);
         }
     }
     acc = wave_sum(acc);
@@ -506,6 +603,13 @@ template <int W, bool PV>
 constexpr size_t team_bytes() {
     return (sizeof(TeamLds<W, PV>) + 15) & ~size_t(15);
 }
+
+static_assert(team_bytes<2, true>() * TierCfg<2>::TPB <= 160 * 1024, "tier 0 LDS");
+static_assert(team_bytes<4, true>() * TierCfg<4>::TPB <= 160 * 1024, "tier 1 LDS");
+static_assert(team_bytes<8, true>() * TierCfg<8>::TPB <= 160 * 1024, "tier 2 LDS");
+static_assert(team_bytes<12, true>() * TierCfg<12>::TPB <= 160 * 1024, "tier 3 LDS");
+static_assert(team_bytes<16, true>() * TierCfg<16>::TPB <= 160 * 1024, "tier 4 LDS");
+static_assert(team_bytes<24, true>() * TierCfg<24>::TPB <= 160 * 1024, "tier 5 LDS");
 
 template <int W, int LMAX, bool PV, bool INSTR>
 static int launch_tier(const CountArgs &a, unsigned grid, hipStream_t s) {
@@ -577,8 +681,6 @@ ARB_DECLARE_DEPTH(4)
 ARB_DECLARE_DEPTH(5)
 ARB_DECLARE_DEPTH(6)
 ARB_DECLARE_DEPTH(7)
-ARB_DECLARE_DEPTH(8)
-ARB_DECLARE_DEPTH(9)
 #undef ARB_DECLARE_DEPTH
 
 }  // namespace arb

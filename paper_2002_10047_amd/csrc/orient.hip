@@ -222,14 +222,16 @@ __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *idx, co
 }
 
 // Rows of at most 64 entries: one wave per row, each lane's destination is the number of
-// smaller entries (entries are distinct).
-__global__ void k_row_sort_small(int64_t n, const int64_t *ooff, int32_t *oidx) {
+// smaller entries (entries are distinct).  Also reduces the largest row length.
+__global__ void k_row_sort_small(int64_t n, const int64_t *ooff, int32_t *oidx, int64_t *stats) {
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t dmax = 0;
     for (int64_t r = wave; r < n; r += nwaves) {
         int64_t s = ooff[r];
-        int d = (int)(ooff[r + 1] - s);
+        int d = (int)min<int64_t>(ooff[r + 1] - s, 0x7fffffff);
+        dmax = d > dmax ? d : dmax;
         if (d <= 1 || d > 64) continue;
         int32_t x = lane < d ? oidx[s + lane] : 0x7fffffff;
         int pos = 0;
@@ -239,24 +241,47 @@ __global__ void k_row_sort_small(int64_t n, const int64_t *ooff, int32_t *oidx) 
         }
         if (lane < d) oidx[s + pos] = x;
     }
+    if (stats && lane == 0 && dmax > 0) atomicMax((unsigned long long *)&stats[1], (unsigned long long)dmax);
 }
 
-// Rows longer than 64: one block per row, bitonic sort in LDS (padded to a power of two).
-__global__ void k_row_sort_big(int64_t n, const int64_t *ooff, int32_t *oidx, int64_t *stats, int32_t *err) {
-    extern __shared__ int32_t buf[];
+constexpr int kMidRow = 2048;
+
+// Rows of 65..2048 entries: one block per row; each element's destination is the count
+// of smaller entries in the row, read back from LDS as broadcasts.
+__global__ void __launch_bounds__(256) k_row_sort_mid(int64_t n, const int64_t *ooff, int32_t *oidx) {
+    __shared__ int32_t buf[kMidRow];
     for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
-        int64_t s = ooff[r];
-        int d = (int)min<int64_t>(ooff[r + 1] - s, 0x7fffffff);
-        if (stats && threadIdx.x == 0 && d > 0)
-            atomicMax((unsigned long long *)&stats[1], (unsigned long long)d);
-        if (d <= 64) continue;
-        if (d > ARB_MAX_ROW_SORT) {
+        const int64_t s = ooff[r];
+        const int64_t d64 = ooff[r + 1] - s;
+        if (d64 <= 64 || d64 > kMidRow) continue;
+        const int d = (int)d64;
+        for (int i = threadIdx.x; i < d; i += blockDim.x) buf[i] = oidx[s + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            const int32_t x = buf[i];
+            int pos = 0;
+            for (int j = 0; j < d; ++j) pos += buf[j] < x;
+            oidx[s + pos] = x;
+        }
+        __syncthreads();
+    }
+}
+
+// Rows longer than 2048: one block per row, bitonic sort in LDS (padded to a power of two).
+__global__ void k_row_sort_big(int64_t n, const int64_t *ooff, int32_t *oidx, int32_t *err) {
+    extern __shared__ int32_t big[];
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const int64_t s = ooff[r];
+        const int64_t d64 = ooff[r + 1] - s;
+        if (d64 <= kMidRow) continue;
+        if (d64 > ARB_MAX_ROW_SORT) {
             if (threadIdx.x == 0) atomicOr(err, (int32_t)kErrRowLong);
             continue;
         }
+        const int d = (int)d64;
         int p2 = 128;
         while (p2 < d) p2 <<= 1;
-        for (int i = threadIdx.x; i < p2; i += blockDim.x) buf[i] = i < d ? oidx[s + i] : 0x7fffffff;
+        for (int i = threadIdx.x; i < p2; i += blockDim.x) big[i] = i < d ? oidx[s + i] : 0x7fffffff;
         __syncthreads();
         for (int size = 2; size <= p2; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -264,13 +289,13 @@ __global__ void k_row_sort_big(int64_t n, const int64_t *ooff, int32_t *oidx, in
                     int lo = 2 * i - (i & (stride - 1));
                     int hi = lo + stride;
                     bool up = (lo & size) == 0;
-                    int32_t a = buf[lo], b = buf[hi];
-                    if ((a > b) == up) { buf[lo] = b; buf[hi] = a; }
+                    int32_t a = big[lo], b = big[hi];
+                    if ((a > b) == up) { big[lo] = b; big[hi] = a; }
                 }
                 __syncthreads();
             }
         }
-        for (int i = threadIdx.x; i < d; i += blockDim.x) oidx[s + i] = buf[i];
+        for (int i = threadIdx.x; i < d; i += blockDim.x) oidx[s + i] = big[i];
         __syncthreads();
     }
 }
@@ -416,9 +441,10 @@ extern "C" int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *
     if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
     if ((rc = exclusive_scan_i64(w.outdeg, out->offsets, n, w.scan_ws, s))) return fail(rc);
     k_dir_fill<<<gv, 256, 0, s>>>(n, g->offsets, g->indices, rank, out->offsets, out->indices);
-    k_row_sort_small<<<gv, 256, 0, s>>>(n, out->offsets, out->indices);
-    k_row_sort_big<<<grid_for(n, 1, 4096), 256, ARB_MAX_ROW_SORT * sizeof(int32_t), s>>>(
-        n, out->offsets, out->indices, stats, w.err);
+    k_row_sort_small<<<gv, 256, 0, s>>>(n, out->offsets, out->indices, stats);
+    k_row_sort_mid<<<grid_for(n, 1, 8192), 256, 0, s>>>(n, out->offsets, out->indices);
+    k_row_sort_big<<<grid_for(n, 64, 256), 256, ARB_MAX_ROW_SORT * sizeof(int32_t), s>>>(
+        n, out->offsets, out->indices, w.err);
     if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
     if (round_out) {
         k_copy_rounds<<<gb, 256, 0, s>>>(n, rnd, round_out);
