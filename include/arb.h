@@ -129,11 +129,14 @@ enum {
 
 typedef struct {
     int schedule;          /* ARB_SCHED_* */
-    int split_min_degree;  /* roots with d+ >= this (degree schedules) are split into one
-                              item per out-neighbour; 0 = never split */
-    float split_min_cost;  /* learned schedule: split roots whose predicted log2(1+work)
-                              is >= this; 0 = never */
-    int persist_blocks_per_cu;  /* persistent grid = 256 x this (1..8) */
+    int split_min_degree;  /* degree schedules: a root with d+ >= this becomes
+                              P = ceil(d+ / split_min_degree) parts (at most 64), each
+                              building the root's induced subgraph and taking every
+                              P-th row of its work; 0 = never split */
+    float split_min_cost;  /* learned schedule: a root whose predicted log2(1+work) y is
+                              >= this becomes P = ceil(2^(y - split_min_cost)) parts;
+                              0 = never split */
+    int persist_blocks_per_cu;  /* persistent grid: up to this many blocks per CU (1..8) */
     int chunk_small;       /* items popped at once by single-wave teams (1..256) */
     const uint16_t *mlp_weights; /* device bf16 weights for ARB_SCHED_LEARNED (8641) */
     const float *features;       /* device float[n][3] from arb_features, ARB_SCHED_LEARNED */
@@ -157,18 +160,27 @@ size_t arb_count_workspace(int64_t n, int64_t m, int k);
  *   k           1 <= k <= ARB_MAX_K (k = 1 gives n, k = 2 gives m)
  *   total_dev   device uint64[1], overwritten with the total
  *   per_vertex  device uint64[n], nullable; overwritten
+ *   per_root    device uint64[n], nullable; overwritten with the number of k-cliques
+ *               whose lowest-ranked vertex is v (the root's share of the total)
  *   work_out    device uint64[n], nullable; overwritten with the per-root work measure
  *               w(v) = sum_{u in N+(v)} d+(u) + ceil(d+(v)/32) * sum_{j=1}^{k-2} c_j(v)
  *               where c_j(v) is the number of j-cliques in G[N+(v)]  (roots with
  *               d+(v) < k-1 and k <= 2 get 0); forces the unsplit schedule
  *   opts        nullable (defaults)
- * Does not synchronise; capture-safe.  Errors: ARB_EINVAL, ARB_EWORKSPACE, ARB_ELIMIT
- * (an item's candidate set above ARB_MAX_LOCAL; reported through arb_count only, as
- * the async form cannot see it: it then leaves total_dev = UINT64_MAX).
+ * Does not synchronise and is capture-safe, except ARB_SCHED_PLAIN, which synchronises
+ * once to size its grids.  Errors: ARB_EINVAL, ARB_EWORKSPACE.  A work item whose
+ * candidate set exceeds ARB_MAX_LOCAL cannot be reported here: the call then leaves
+ * total_dev = UINT64_MAX (arb_count turns that into ARB_ELIMIT).
  */
 int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,
-                    uint64_t *work_out, const arb_count_opts *opts,
+                    uint64_t *per_root, uint64_t *work_out, const arb_count_opts *opts,
                     void *ws, size_t ws_bytes, void *stream);
+
+/* out[g] = sum of in[offsets[g] .. offsets[g+1]) for g < G (device arrays; offsets has
+ * G+1 entries).  With per_root counts mapped to original ids (arb_permute_u64) and a
+ * disjoint union of G graphs, this yields the per-graph totals of a batch. */
+int arb_segment_sum_u64(const uint64_t *in, const int64_t *offsets, int64_t G, uint64_t *out,
+                        void *stream);
 
 /* Synchronous arb_count_async that also checks dg first; returns the total, or 0 with
  * arb_last_error() != ARB_OK on failure.  Synchronises the stream. */

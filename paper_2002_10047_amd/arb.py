@@ -70,7 +70,8 @@ _sigs = {
     "arb_permute_u64": ([P, P, P, I64, P], I32),
     "arb_count_default_opts": ([P], None),
     "arb_count_workspace": ([I64, I64, I32], SZ),
-    "arb_count_async": ([P, I32, P, P, P, P, P, SZ, P], I32),
+    "arb_count_async": ([P, I32, P, P, P, P, P, P, SZ, P], I32),
+    "arb_segment_sum_u64": ([P, P, I64, P, P], I32),
     "arb_count": ([P, I32, P, P, P, SZ, P], ctypes.c_uint64),
     "arb_features": ([P, P, P, P, P], I32),
     "arb_mlp_forward": ([P, P, I64, P, P, P], I32),
@@ -205,14 +206,15 @@ class CountWorkspace:
         self.buf = _ws(self.bytes, ooff.device)
 
 
-def arb_count_async(ooff, oidx, k, total=None, per_vertex=None, work=None, opts=None, ws=None, stream=None):
+def arb_count_async(ooff, oidx, k, total=None, per_vertex=None, work=None, opts=None, ws=None, stream=None,
+                    per_root=None):
     """Enqueue arb_count_async; returns the device total tensor (int64 holding uint64)."""
     dg = _ocsr(ooff, oidx)
     if ws is None:
         ws = CountWorkspace(ooff, oidx, k)
     if total is None:
         total = torch.empty(1, dtype=torch.int64, device=ooff.device)
-    rc = _lib.arb_count_async(ctypes.byref(dg), int(k), _ptr(total), _ptr(per_vertex), _ptr(work),
+    rc = _lib.arb_count_async(ctypes.byref(dg), int(k), _ptr(total), _ptr(per_vertex), _ptr(per_root), _ptr(work),
                               ctypes.byref(opts) if opts is not None else None, _ptr(ws.buf), ws.buf.numel(),
                               _stream(stream))
     _check(rc, "arb_count_async")
@@ -245,6 +247,15 @@ def arb_profile_read():
     items = (ctypes.c_int64 * 6)()
     _check(_lib.arb_profile_read(ms, items), "arb_profile_read")
     return np.array(ms[:], np.float64), np.array(items[:], np.int64)
+
+
+def arb_segment_sum_u64(values, offsets, stream=None):
+    """Per-segment sums of a device uint64 (int64-typed) tensor; offsets: device int64[G+1]."""
+    G = offsets.numel() - 1
+    out = torch.empty(max(G, 1), dtype=torch.int64, device=values.device)
+    _check(_lib.arb_segment_sum_u64(_ptr(values), _ptr(offsets), G, _ptr(out), _stream(stream)),
+           "arb_segment_sum_u64")
+    return out[:G]
 
 
 # ------------------------------------------------------------------ learned schedule

@@ -8,9 +8,43 @@ __global__ void k_permute_u64(const int32_t *rank, const uint64_t *in, uint64_t 
         out[v] = in[rank[v]];
 }
 
+// One block per segment, 64-bit sums reduced in a fixed order.
+__global__ void k_segment_sum(const unsigned long long *in, const int64_t *off, int64_t G, unsigned long long *out) {
+    __shared__ unsigned long long red[256];
+    for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
+        unsigned long long s = 0;
+        for (int64_t i = off[g] + threadIdx.x; i < off[g + 1]; i += blockDim.x) s += in[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[g] = red[0];
+        __syncthreads();
+    }
+}
+
 }  // namespace arb
 
 using namespace arb;
+
+extern "C" int arb_segment_sum_u64(const uint64_t *in, const int64_t *offsets, int64_t G, uint64_t *out, void *stream) {
+    if (G < 0 || (G > 0 && (!in || !offsets || !out))) {
+        set_error(ARB_EINVAL);
+        return ARB_EINVAL;
+    }
+    if (G > 0) {
+        k_segment_sum<<<grid_for(G, 1, 4096), 256, 0, as_stream(stream)>>>(
+            reinterpret_cast<const unsigned long long *>(in), offsets, G, reinterpret_cast<unsigned long long *>(out));
+        if (hipGetLastError() != hipSuccess) {
+            set_error(ARB_EHIP);
+            return ARB_EHIP;
+        }
+    }
+    set_error(ARB_OK);
+    return ARB_OK;
+}
 
 extern "C" int arb_permute_u64(const int32_t *rank, const uint64_t *in, uint64_t *out, int64_t n, void *stream) {
     if (n < 0 || (n > 0 && (!rank || !in || !out)) || in == out) {

@@ -25,6 +25,11 @@ __global__ void k_count_k2(int64_t n, const int64_t *off, const int32_t *idx, un
     }
 }
 
+__global__ void k_root_outdeg(int64_t n, const int64_t *off, unsigned long long *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (unsigned long long)(off[i + 1] - off[i]);
+}
+
 __global__ void k_check_oriented(int64_t n, const int64_t *off, const int32_t *idx, int64_t m, int32_t *err) {
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -62,47 +67,67 @@ __global__ void k_finish(const int32_t *err, unsigned long long *total) {
 
 constexpr uint32_t kCostMax = (1u << 28) - 1;
 constexpr int kDeadTier = 7;
+constexpr int kMaxParts = 64;
 
-__device__ __forceinline__ bool root_split(int64_t d, int split_deg, const float *lcost, float split_cost, int64_t v) {
-    if (d > ARB_MAX_LOCAL) return true;
-    if (lcost) return split_cost > 0.f && lcost[v] >= split_cost;
-    return split_deg > 0 && d >= split_deg;
+// Parts of a root: degree schedule P = ceil(d / split_deg); learned schedule
+// P = ceil(2^(y - split_cost)) with y the predicted log2(1 + work); at most 64 and at
+// most d.  Roots too large for LDS (d > ARB_MAX_LOCAL) are split per out-neighbour.
+__device__ __forceinline__ int root_parts(int64_t d, int split_deg, const float *lcost, float split_cost, int64_t v) {
+    int64_t P = 1;
+    if (lcost) {
+        if (split_cost > 0.f && lcost[v] >= split_cost)
+            P = (int64_t)ceilf(exp2f(fminf(lcost[v] - split_cost, 7.f)));
+    } else if (split_deg > 0 && d >= split_deg) {
+        P = (d + split_deg - 1) / split_deg;
+    }
+    if (P > kMaxParts) P = kMaxParts;
+    if (P > d) P = d;
+    return (int)(P < 1 ? 1 : P);
 }
 
-__global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *lcost, uint32_t *key, int32_t *val) {
+__global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *lcost, int split_deg, float split_cost,
+                            uint32_t *key, int32_t *val, int32_t *parts) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = off[v + 1] - off[v];
         uint32_t kk;
+        int P = 0;
         if (d < k - 1) {
             kk = ((uint32_t)kDeadTier << 28) | kCostMax;
         } else {
             int t = tier_of(d);
-            if (t < 0) t = kNumTiers - 1;
-            float c = lcost ? fminf(fmaxf(lcost[v], 0.f) * 4096.f, (float)kCostMax) : (float)d;
-            uint32_t cq = (uint32_t)c;
-            if (cq > kCostMax) cq = kCostMax;
+            if (t < 0) {                       // per-out-neighbour items in the largest tier
+                t = kNumTiers - 1;
+                P = -1;
+            } else {
+                P = root_parts(d, split_deg, lcost, split_cost, v);
+            }
+            const float per = P > 0 ? (float)P : (float)d;
+            float c = lcost ? fmaxf(lcost[v] - log2f(per), 0.f) * 4096.f : (float)d / per;
+            uint32_t cq = (uint32_t)fminf(c, (float)kCostMax);
             kk = ((uint32_t)t << 28) | (kCostMax - cq);
         }
         key[v] = kk;
         val[v] = (int32_t)v;
+        parts[v] = P;
     }
 }
 
-__global__ void k_sorted_units(int64_t n, const int64_t *off, const uint32_t *key, const int32_t *val, int split_deg,
-                               const float *lcost, float split_cost, int64_t *ucnt) {
+// items of the root at sorted position p: 0 (dead), P (parts) or d (per out-neighbour)
+__global__ void k_sorted_units(int64_t n, const int64_t *off, const uint32_t *key, const int32_t *val,
+                               const int32_t *parts, int64_t *ucnt) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         int64_t u = 0;
         if ((key[p] >> 28) != (uint32_t)kDeadTier) {
             const int32_t v = val[p];
-            const int64_t d = off[v + 1] - off[v];
-            u = root_split(d, split_deg, lcost, split_cost, v) ? d : 1;
+            const int P = parts[v];
+            u = P > 0 ? P : off[v + 1] - off[v];
         }
         ucnt[p] = u;
     }
 }
 
-__global__ void k_expand(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *val, const int64_t *uoff,
-                         int32_t *iroot, int32_t *ichild) {
+__global__ void k_expand(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *val, const int32_t *parts,
+                         const int64_t *uoff, int32_t *iroot, int32_t *ichild) {
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -110,14 +135,20 @@ __global__ void k_expand(int64_t n, const int64_t *off, const int32_t *idx, cons
         const int64_t b = uoff[p], c = uoff[p + 1] - b;
         if (c == 0) continue;
         const int32_t v = val[p];
-        if (c == 1) {      // whole root (a split root has d+ >= k-1 >= 2 items)
+        const int P = parts[v];
+        if (P == 1) {
             if (lane == 0) { iroot[b] = v; ichild[b] = -1; }
-            continue;
-        }
-        const int64_t s = off[v];
-        for (int64_t i = lane; i < c; i += 64) {
-            iroot[b + i] = v;
-            ichild[b + i] = idx[s + i];
+        } else if (P > 1) {
+            for (int i = lane; i < P; i += 64) {
+                iroot[b + i] = v;
+                ichild[b + i] = -2 - (i * 128 + P);
+            }
+        } else {
+            const int64_t s = off[v];
+            for (int64_t i = lane; i < c; i += 64) {
+                iroot[b + i] = v;
+                ichild[b + i] = idx[s + i];
+            }
         }
     }
 }
@@ -141,6 +172,7 @@ struct CountWs {
     uint32_t *key, *key_alt;
     int32_t *val, *val_alt;
     int32_t *iroot, *ichild;
+    int32_t *parts;       // n
     float *lcost;         // n
     unsigned long long *tot;  // total of the synchronous arb_count
     void *scan_ws, *radix_ws;
@@ -159,6 +191,7 @@ static size_t carve_count(Carver &c, int64_t n, int64_t m, CountWs *w) {
     w->val_alt = c.take<int32_t>(nn);
     w->iroot = c.take<int32_t>(U);
     w->ichild = c.take<int32_t>(U);
+    w->parts = c.take<int32_t>(nn);
     w->lcost = c.take<float>(nn);
     w->tot = c.take<unsigned long long>(4);
     w->scan_ws = c.take<char>(scan_workspace(nn + 1));
@@ -253,8 +286,8 @@ extern "C" int arb_check_oriented(const arb_ocsr *dg, void *ws, size_t ws_bytes,
     return rc;
 }
 
-static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *work_out,
-                      const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s) {
+static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *per_root_out,
+                      uint64_t *work_out, const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s) {
     if (!ocsr_ok(dg) || !total_dev || !ws) return ARB_EINVAL;
     if (k < 1 || k > ARB_MAX_K) return ARB_EINVAL;
     arb_count_opts opts;
@@ -270,10 +303,17 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     unsigned long long *total = reinterpret_cast<unsigned long long *>(total_dev);
     unsigned long long *pv = reinterpret_cast<unsigned long long *>(per_vertex);
     unsigned long long *work = reinterpret_cast<unsigned long long *>(work_out);
+    unsigned long long *per_root = reinterpret_cast<unsigned long long *>(per_root_out);
     int rc;
     const unsigned gb = grid_for(n, 256, 4096);
     if (pv) { k_u64_fill<<<gb, 256, 0, s>>>(pv, 0ull, n); ARB_CHECK_LAUNCH(); }
     if (work) { k_u64_fill<<<gb, 256, 0, s>>>(work, 0ull, n); ARB_CHECK_LAUNCH(); }
+    if (per_root) { k_u64_fill<<<gb, 256, 0, s>>>(per_root, 0ull, n); ARB_CHECK_LAUNCH(); }
+    if (per_root && k <= 2) {
+        if (k == 1) k_u64_fill<<<gb, 256, 0, s>>>(per_root, 1ull, n);
+        else k_root_outdeg<<<gb, 256, 0, s>>>(n, dg->offsets, per_root);
+        ARB_CHECK_LAUNCH();
+    }
     if (k == 1) { k_count_k1<<<gb, 256, 0, s>>>(n, total, pv); ARB_CHECK_LAUNCH(); return ARB_OK; }
     if (k == 2) { k_count_k2<<<gb, 256, 0, s>>>(n, dg->offsets, dg->indices, total, pv); ARB_CHECK_LAUNCH(); return ARB_OK; }
     k_u64_fill<<<1, 64, 0, s>>>(total, 0ull, 1);
@@ -295,13 +335,14 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     }
     const int split_deg = work ? 0 : opts.split_min_degree;
     const float split_cost = work ? 0.f : opts.split_min_cost;
-    k_root_keys<<<gb, 256, 0, s>>>(n, dg->offsets, k, lcost, w.key, w.val);
+    k_root_keys<<<gb, 256, 0, s>>>(n, dg->offsets, k, lcost, split_deg, split_cost, w.key, w.val, w.parts);
     ARB_CHECK_LAUNCH();
     if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, n, 31, w.radix_ws, s))) return rc;
-    k_sorted_units<<<gb, 256, 0, s>>>(n, dg->offsets, w.key, w.val, split_deg, lcost, split_cost, w.ucnt);
+    k_sorted_units<<<gb, 256, 0, s>>>(n, dg->offsets, w.key, w.val, w.parts, w.ucnt);
     ARB_CHECK_LAUNCH();
     if ((rc = exclusive_scan_i64(w.ucnt, w.ucnt, n, w.scan_ws, s))) return rc;
-    k_expand<<<grid_for(n * 64, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, w.val, w.ucnt, w.iroot, w.ichild);
+    k_expand<<<grid_for(n * 64, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, w.val, w.parts, w.ucnt,
+                                                         w.iroot, w.ichild);
     ARB_CHECK_LAUNCH();
     k_segments<<<gb, 256, 0, s>>>(n, w.key, w.ucnt, w.seg);
     ARB_CHECK_LAUNCH();
@@ -337,6 +378,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
         a.head = w.heads + t;
         a.total = total;
         a.pv = pv;
+        a.per_root = per_root;
         a.work = work;
         a.err = w.err;
         a.chunk = t <= 1 ? opts.chunk_small : 1;
@@ -369,9 +411,9 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
 }
 
 extern "C" int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,
-                               uint64_t *work_out, const arb_count_opts *opts, void *ws, size_t ws_bytes,
-                               void *stream) {
-    int rc = count_impl(dg, k, total_dev, per_vertex, work_out, opts, ws, ws_bytes, as_stream(stream));
+                               uint64_t *per_root, uint64_t *work_out, const arb_count_opts *opts, void *ws,
+                               size_t ws_bytes, void *stream) {
+    int rc = count_impl(dg, k, total_dev, per_vertex, per_root, work_out, opts, ws, ws_bytes, as_stream(stream));
     set_error(rc);
     return rc;
 }
@@ -385,7 +427,7 @@ extern "C" uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex, c
     Carver cv(ws);
     CountWs w;
     carve_count(cv, dg->n, dg->m, &w);
-    int rc = count_impl(dg, k, reinterpret_cast<uint64_t *>(w.tot), per_vertex, nullptr, opts, ws, ws_bytes, s);
+    int rc = count_impl(dg, k, reinterpret_cast<uint64_t *>(w.tot), per_vertex, nullptr, nullptr, opts, ws, ws_bytes, s);
     if (rc) { set_error(rc); return 0; }
     uint64_t h = 0;
     if (hipMemcpyAsync(&h, w.tot, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||

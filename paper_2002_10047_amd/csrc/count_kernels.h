@@ -203,6 +203,7 @@ struct CountArgs {
     int *head;                     // queue head (persistent)
     unsigned long long *total;
     unsigned long long *pv;        // nullable
+    unsigned long long *per_root;  // nullable: cliques whose lowest-ranked vertex is the root
     unsigned long long *work;      // nullable
     int32_t *err;
     int chunk;
@@ -370,6 +371,14 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
     const uint64_t below = lanes_below_mask();
 
     team_sync<TW, TPB>();            // previous item finished with the LDS
+    // child >= 0: the pair item (root, child); child == -1: the whole root; child <= -2:
+    // part `part` of P of a split root, which takes every P-th row of the root's work
+    int P = 1, part = 0;
+    if (child < -1) {
+        const int q = -child - 2;
+        P = q & 127;
+        part = q >> 7;
+    }
     int need;
     if (child < 0) {
         const int64_t s0 = a.off[root];
@@ -454,7 +463,9 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
         // second level: read N+(u) for each member u (four 64-lane chunks in flight per
         // wave) and keep the entries that are members; rows ascend, so a list is left as
         // soon as it passes the largest member
-        for (int i = wv; i < d; i += TW) {
+        // k-1 = 2 (no bit rows): the gather is the whole work, so parts split its rows
+        const int g0 = need == 2 ? part + P * wv : wv, gstep = need == 2 ? P * TW : TW;
+        for (int i = g0; i < d; i += gstep) {
             const int32_t u = T->S[i];
             const int64_t s = a.off[u], e = a.off[u + 1];
             if constexpr (INSTR) {
@@ -499,7 +510,7 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
             AS3<uint32_t> *ring = T->ring[wv];
             unsigned head = 0, tail = 0;
             const int pneed = need - 2;
-            for (int x = wv; x < d; x += TW) {
+            for (int x = part + P * wv; x < d; x += P * TW) {
                 uint32_t bits = 0;
                 if (lane < W) {
                     bits = T->rows[x * Lds::RS + lane];
@@ -543,8 +554,10 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
         }
     }
 
+    unsigned long long item = 0;
+    if (PV || a.per_root != nullptr) item = team_sum<TW, TPB>(T, mine, wv, lane);
+    if (a.per_root != nullptr && tlid == 0 && item) atomicAdd(&a.per_root[root], item);
     if constexpr (PV || INSTR) {
-        const unsigned long long item = team_sum<TW, TPB>(T, mine, wv, lane);
         if constexpr (PV) {
             for (int i = tlid; i < d; i += TT) {
                 unsigned long long c = T->cnt[i];
