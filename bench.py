@@ -39,8 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--ks", default="3,4,5")
     ap.add_argument("--eps", type=float, default=1.0)
-    ap.add_argument("--schedule", default="persistent", choices=["plain", "persistent", "learned"])
-    ap.add_argument("--split", type=int, default=0, help="split roots with d+ >= this (0: never)")
+    ap.add_argument("--schedule", default="learned", choices=["plain", "persistent", "degree", "learned"])
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -153,35 +153,63 @@ def main():
     g = gg.config_graph("c2")
     log(f"graph: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
     off, idx = arb.to_device_csr(g)
-    sched = {"plain": arb.ARB_SCHED_PLAIN, "persistent": arb.ARB_SCHED_PERSISTENT,
-             "learned": arb.ARB_SCHED_LEARNED}[a.schedule]
-    opts = arb.count_opts(schedule=sched, split_min_degree=a.split)
     o = arb.arb_orient(off, idx, eps=a.eps)
     wss = {k: arb.CountWorkspace(o["ooff"], o["oidx"], k) for k in ks}
     totals = {k: torch.empty(1, dtype=torch.int64, device="cuda") for k in ks}
+    from paper_2002_10047_amd import learn
+    weights = {k: learn.load_weights(k) for k in ks}
+    missing = [k for k in ks if weights[k] is None]
+    if missing:
+        raise SystemExit(f"no trained cost model for k={missing}: run python -m paper_2002_10047_amd.train_cost")
+    feat = arb.arb_features(o["ooff"], o["oidx"], o["round"], o["rank"])
 
-    def step():
-        oo = arb.arb_orient(off, idx, eps=a.eps)
+    # ---------------------------------------------------------------- tuning (untimed)
+    schedules = {}
+    t_tune = time.time()
+    for name in ("degree", "learned"):
+        per_k = {}
         for k in ks:
-            arb.arb_count_async(oo["ooff"], oo["oidx"], k, total=totals[k], opts=opts, ws=wss[k])
+            if name == "learned":
+                op = arb.count_opts(schedule=arb.ARB_SCHED_LEARNED, mlp_weights=weights[k], features=feat)
+            else:
+                op = arb.count_opts(schedule=arb.ARB_SCHED_PERSISTENT)
+            if not a.no_tune:
+                ms = arb.arb_autotune(o["ooff"], o["oidx"], k, op, trials=2, ws=wss[k])
+                log(f"tuned {name} k={k}: {ms:.3f} ms {arb.opts_dict(op)}")
+            per_k[k] = op
+        schedules[name] = per_k
+    schedules["plain"] = {k: arb.count_opts(schedule=arb.ARB_SCHED_PLAIN) for k in ks}
+    log(f"tuning took {time.time() - t_tune:.1f}s")
+
+    def step(name):
+        oo = arb.arb_orient(off, idx, eps=a.eps)
+        if name == "learned":
+            f = arb.arb_features(oo["ooff"], oo["oidx"], oo["round"], oo["rank"])
+            for k in ks:
+                schedules[name][k].features = f.data_ptr()
+                schedules[name][k]._keep = (weights[k], f)
+        for k in ks:
+            arb.arb_count_async(oo["ooff"], oo["oidx"], k, total=totals[k], opts=schedules[name][k], ws=wss[k])
         return oo
 
-    for i in range(a.warmup):
-        step()
+    def timed(name):
+        for i in range(a.warmup):
+            step(name)
+            torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{a.warmup} done")
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wall0 = time.time()
-    ev0.record()
-    for i in range(a.steps):
-        o = step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.time() - wall0
-    ms_step = ev0.elapsed_time(ev1) / a.steps
-    tot = {k: int(totals[k].cpu().numpy().view(np.uint64)[0]) for k in ks}
-    log(f"timed {a.steps} steps: {ms_step:.3f} ms/step (wall {wall:.2f}s) totals {tot}")
+        ev0.record()
+        for i in range(a.steps):
+            step(name)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / a.steps
+        tot = {k: int(totals[k].cpu().numpy().view(np.uint64)[0]) for k in ks}
+        log(f"{name}: {ms:.3f} ms/step over {a.steps} steps, totals {tot}")
+        return ms, tot
+
+    main_name = a.schedule if a.schedule != "persistent" else "degree"
+    ms_step, tot = timed(main_name)
     cliques = sum(tot.values())
     value = cliques / (ms_step / 1e3)
     out = {
@@ -190,9 +218,22 @@ def main():
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": "rmat20_k345", "graph": "R-MAT scale 20, 2^24 samples, a=.57 b=.19 c=.19 d=.05, "
-                   "seed 2, deduped", "n": g.n, "m": g.m, "k": ks, "eps": a.eps, "schedule": a.schedule,
-                   "split_min_degree": a.split, "totals": {str(k): tot[k] for k in ks}},
+                   "seed 2, deduped", "n": g.n, "m": g.m, "k": ks, "eps": a.eps, "schedule": main_name,
+                   "opts": {str(k): arb.opts_dict(schedules[main_name][k]) for k in ks},
+                   "totals": {str(k): tot[k] for k in ks}},
     }
+    if not a.no_extras:
+        cmp = {main_name: ms_step}
+        for name in ("learned", "degree", "plain"):
+            if name not in cmp:
+                ms_o, tot_o = timed(name)
+                if tot_o != tot:
+                    raise SystemExit(f"schedule {name} changed the totals: {tot_o} vs {tot}")
+                cmp[name] = ms_o
+        out["schedules_ms_per_step"] = cmp
+        out["learned_gain_vs_degree"] = cmp["degree"] / cmp["learned"]
+        out["learned_gain_vs_plain"] = cmp["plain"] / cmp["learned"]
+        opts = schedules[main_name][ks[0]]
     if a.no_extras:
         print(json.dumps(out), flush=True)
         return
@@ -205,7 +246,7 @@ def main():
     e[1].record()
     for i, k in enumerate(ks):
         e[2 + 2 * i].record()
-        arb.arb_count_async(o["ooff"], o["oidx"], k, total=totals[k], opts=opts, ws=wss[k])
+        arb.arb_count_async(o["ooff"], o["oidx"], k, total=totals[k], opts=schedules[main_name][k], ws=wss[k])
         e[3 + 2 * i].record()
     torch.cuda.synchronize()
     t_orient = e[0].elapsed_time(e[1]) / 1e3
@@ -223,7 +264,7 @@ def main():
     arb.arb_profile_enable(True)
     tiers = {}
     for k in ks:
-        arb.arb_count_async(o["ooff"], o["oidx"], k, total=totals[k], opts=opts, ws=wss[k])
+        arb.arb_count_async(o["ooff"], o["oidx"], k, total=totals[k], opts=schedules[main_name][k], ws=wss[k])
         ms, items = arb.arb_profile_read()
         tiers[k] = (ms, items)
     arb.arb_profile_enable(False)

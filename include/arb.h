@@ -46,7 +46,8 @@ enum {
     ARB_EGRAPH = 2,      /* input graph violates the layout above */
     ARB_EWORKSPACE = 3,  /* workspace smaller than the matching *_workspace() size */
     ARB_EHIP = 4,        /* a HIP runtime call failed */
-    ARB_ELIMIT = 5       /* an implementation limit was exceeded (see ARB_MAX_*) */
+    ARB_ELIMIT = 5,      /* an implementation limit was exceeded (see ARB_MAX_*) */
+    ARB_EMISMATCH = 6    /* two schedules gave different totals (a library defect) */
 };
 
 #define ARB_MAX_K 10            /* largest clique size the counting kernels take */
@@ -138,6 +139,9 @@ typedef struct {
                               0 = never split */
     int persist_blocks_per_cu;  /* persistent grid: up to this many blocks per CU (1..8) */
     int chunk_small;       /* items popped at once by single-wave teams (1..256) */
+    int bitmap_max_span;   /* membership test of the second level: an id-range bitmap when
+                              the members' ids span fewer than this (and the tier's
+                              capacity), else a hash; 0 = always hash */
     const uint16_t *mlp_weights; /* device bf16 weights for ARB_SCHED_LEARNED (8641) */
     const float *features;       /* device float[n][3] from arb_features, ARB_SCHED_LEARNED */
 } arb_count_opts;
@@ -196,6 +200,19 @@ uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex,
 #define ARB_NUM_TIERS 6
 int arb_profile_enable(int on);
 int arb_profile_read(float *tier_ms, int64_t *tier_items);
+
+/*
+ * Autotuner: coordinate descent (two passes) over the split threshold
+ * (split_min_degree, or split_min_cost for ARB_SCHED_LEARNED), persist_blocks_per_cu,
+ * chunk_small and bitmap_max_span for this graph and k.  Each candidate runs once to
+ * warm up and then `trials` times; its time is the fastest run (HIP events on the
+ * stream).  Every candidate's total must equal the first one's, else ARB_EMISMATCH.
+ * opts: in, the schedule (and weights/features when learned) and starting values;
+ * out, the fastest configuration found.  best_ms (host, nullable): its time.
+ * Synchronises; workspace as arb_count.
+ */
+int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int trials, float *best_ms,
+                 void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- learned schedule */
 

@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
                       "(hipcc --offload-arch=gfx950); there is no CPU fallback")
 _lib = ctypes.CDLL(LIB_PATH)
 
-ARB_OK, ARB_EINVAL, ARB_EGRAPH, ARB_EWORKSPACE, ARB_EHIP, ARB_ELIMIT = range(6)
+ARB_OK, ARB_EINVAL, ARB_EGRAPH, ARB_EWORKSPACE, ARB_EHIP, ARB_ELIMIT, ARB_EMISMATCH = range(7)
 ARB_SCHED_PLAIN, ARB_SCHED_PERSISTENT, ARB_SCHED_LEARNED = range(3)
 
 
@@ -56,7 +56,7 @@ class ArbOcsr(ctypes.Structure):
 class ArbCountOpts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("split_min_degree", ctypes.c_int),
                 ("split_min_cost", ctypes.c_float), ("persist_blocks_per_cu", ctypes.c_int),
-                ("chunk_small", ctypes.c_int), ("mlp_weights", ctypes.c_void_p),
+                ("chunk_small", ctypes.c_int), ("bitmap_max_span", ctypes.c_int), ("mlp_weights", ctypes.c_void_p),
                 ("features", ctypes.c_void_p)]
 
 
@@ -80,6 +80,7 @@ _sigs = {
     "arb_mse_grad": ([P, P, I64, P, P, P], I32),
     "arb_adam_step": ([P, P, P, P, P, FLT, I32, P], I32),
     "arb_to_bf16": ([P, P, I64, P], I32),
+    "arb_autotune": ([P, I32, P, I32, P, P, SZ, P], I32),
     "arb_profile_enable": ([I32], I32),
     "arb_profile_read": ([P, P], I32),
     "arb_last_error": ([], I32),
@@ -183,7 +184,7 @@ def arb_permute_u64(rank, values, stream=None):
 # ------------------------------------------------------------------ counting
 
 def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost=0.0,
-               persist_blocks_per_cu=8, chunk_small=16, mlp_weights=None, features=None):
+               persist_blocks_per_cu=8, chunk_small=16, mlp_weights=None, features=None, bitmap_max_span=1 << 30):
     o = ArbCountOpts()
     _lib.arb_count_default_opts(ctypes.byref(o))
     o.schedule = int(schedule)
@@ -191,10 +192,28 @@ def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost
     o.split_min_cost = float(split_min_cost)
     o.persist_blocks_per_cu = int(persist_blocks_per_cu)
     o.chunk_small = int(chunk_small)
+    o.bitmap_max_span = int(bitmap_max_span)
     o.mlp_weights = mlp_weights.data_ptr() if mlp_weights is not None else None
     o.features = features.data_ptr() if features is not None else None
     o._keep = (mlp_weights, features)
     return o
+
+
+def opts_dict(o):
+    return {"schedule": o.schedule, "split_min_degree": o.split_min_degree, "split_min_cost": o.split_min_cost,
+            "persist_blocks_per_cu": o.persist_blocks_per_cu, "chunk_small": o.chunk_small,
+            "bitmap_max_span": o.bitmap_max_span}
+
+
+def arb_autotune(ooff, oidx, k, opts, trials=3, ws=None, stream=None):
+    """Tunes opts in place (see include/arb.h); returns the best time in ms."""
+    dg = _ocsr(ooff, oidx)
+    if ws is None:
+        ws = CountWorkspace(ooff, oidx, k)
+    ms = ctypes.c_float(0.0)
+    _check(_lib.arb_autotune(ctypes.byref(dg), int(k), ctypes.byref(opts), int(trials), ctypes.byref(ms), _ptr(ws.buf),
+                             ws.buf.numel(), _stream(stream)), "arb_autotune")
+    return float(ms.value)
 
 
 class CountWorkspace:

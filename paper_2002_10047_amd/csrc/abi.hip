@@ -72,6 +72,7 @@ extern "C" const char *arb_error_string(int code) {
         case ARB_EWORKSPACE: return "workspace too small";
         case ARB_EHIP: return "HIP runtime error";
         case ARB_ELIMIT: return "implementation limit exceeded";
+        case ARB_EMISMATCH: return "schedules disagree on the total";
         default: return "unknown error";
     }
 }

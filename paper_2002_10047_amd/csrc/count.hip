@@ -1,5 +1,9 @@
 // Host side of the counting path: k <= 2, the directed-graph check, the work schedule
 // (root sort by tier and cost, expansion into items) and the tier launches.
+#include <string.h>
+
+#include <vector>
+
 #include "count_kernels.h"
 
 namespace arb {
@@ -249,6 +253,7 @@ extern "C" void arb_count_default_opts(arb_count_opts *o) {
     o->split_min_cost = 0.f;
     o->persist_blocks_per_cu = 8;
     o->chunk_small = 16;
+    o->bitmap_max_span = 1 << 30;
     o->mlp_weights = nullptr;
     o->features = nullptr;
 }
@@ -297,6 +302,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     if (opts.schedule == ARB_SCHED_LEARNED && (!opts.mlp_weights || !opts.features)) return ARB_EINVAL;
     if (opts.persist_blocks_per_cu < 1 || opts.persist_blocks_per_cu > 8) return ARB_EINVAL;
     if (opts.chunk_small < 1 || opts.chunk_small > 256) return ARB_EINVAL;
+    if (opts.bitmap_max_span < 0) return ARB_EINVAL;
     if (opts.split_min_degree < 0 || !(opts.split_min_cost >= 0.f)) return ARB_EINVAL;
     const int64_t n = dg->n, m = dg->m;
     if (ws_bytes < arb_count_workspace(n, m, k)) return ARB_EWORKSPACE;
@@ -381,7 +387,8 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
         a.per_root = per_root;
         a.work = work;
         a.err = w.err;
-        a.chunk = t <= 1 ? opts.chunk_small : 1;
+        a.chunk = t == 0 ? opts.chunk_small : 1;
+        a.span_max = opts.bitmap_max_span;
         a.persistent = plain ? 0 : 1;
         a.one_item_per_team = plain ? 1 : 0;
         const int tpb = tier_teams_per_block(t);
@@ -473,4 +480,86 @@ extern "C" int arb_profile_read(float *tier_ms, int64_t *tier_items) {
     }
     set_error(ARB_OK);
     return ARB_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+namespace {
+
+struct TuneSpace {
+    std::vector<int> split_deg{0, 24, 48, 96, 192};
+    std::vector<float> split_cost{0.f, 10.f, 12.f, 14.f, 16.f, 18.f};
+    std::vector<int> blocks{2, 4, 8};
+    std::vector<int> chunk{4, 16, 64};
+    std::vector<int> span{0, 1 << 30};
+};
+
+}  // namespace
+
+extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int trials, float *best_ms,
+                            void *ws, size_t ws_bytes, void *stream) {
+    hipStream_t s = as_stream(stream);
+    auto fail = [](int rc) { set_error(rc); return rc; };
+    if (!ocsr_ok(dg) || !opts || !ws || trials < 1 || trials > 100) return fail(ARB_EINVAL);
+    if (ws_bytes < arb_count_workspace(dg->n, dg->m, k)) return fail(ARB_EWORKSPACE);
+    Carver cv(ws);
+    CountWs w;
+    carve_count(cv, dg->n, dg->m, &w);
+    uint64_t *tot = reinterpret_cast<uint64_t *>(w.tot);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ARB_EHIP);
+    uint64_t ref_total = 0;
+    bool have_ref = false;
+    int rc = ARB_OK;
+    // time one configuration: one warm-up, then the best of `trials`; totals must agree
+    auto measure = [&](const arb_count_opts &o, float *ms_out) -> int {
+        float best = 1e30f;
+        for (int t = 0; t <= trials; ++t) {
+            if (hipEventRecord(e0, s) != hipSuccess) return ARB_EHIP;
+            int r = count_impl(dg, k, tot, nullptr, nullptr, nullptr, &o, ws, ws_bytes, s);
+            if (r) return r;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ARB_EHIP;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return ARB_EHIP;
+            if (t > 0 && ms < best) best = ms;
+        }
+        uint64_t h = 0;
+        if (hipMemcpy(&h, tot, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return ARB_EHIP;
+        if (h == ~0ull) return ARB_ELIMIT;
+        if (!have_ref) { ref_total = h; have_ref = true; }
+        else if (h != ref_total) return ARB_EMISMATCH;
+        *ms_out = best;
+        return ARB_OK;
+    };
+    TuneSpace sp;
+    arb_count_opts cur = *opts;
+    if (cur.schedule == ARB_SCHED_PLAIN) cur.schedule = ARB_SCHED_PERSISTENT;
+    const bool learned = cur.schedule == ARB_SCHED_LEARNED;
+    float cur_ms = 0.f;
+    if ((rc = measure(cur, &cur_ms))) goto out;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int param = 0; param < 4; ++param) {
+            const int nv = param == 0 ? (learned ? (int)sp.split_cost.size() : (int)sp.split_deg.size())
+                         : param == 1 ? (int)sp.blocks.size() : param == 2 ? (int)sp.chunk.size() : (int)sp.span.size();
+            for (int i = 0; i < nv; ++i) {
+                arb_count_opts o = cur;
+                if (param == 0) {
+                    if (learned) o.split_min_cost = sp.split_cost[i];
+                    else o.split_min_degree = sp.split_deg[i];
+                } else if (param == 1) o.persist_blocks_per_cu = sp.blocks[i];
+                else if (param == 2) o.chunk_small = sp.chunk[i];
+                else o.bitmap_max_span = sp.span[i];
+                if (memcmp(&o, &cur, sizeof(o)) == 0) continue;
+                float ms = 0.f;
+                if ((rc = measure(o, &ms))) goto out;
+                if (ms < cur_ms) { cur = o; cur_ms = ms; }
+            }
+        }
+    }
+    *opts = cur;
+    if (best_ms) *best_ms = cur_ms;
+out:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return fail(rc);
 }

@@ -207,6 +207,7 @@ struct CountArgs {
     unsigned long long *work;      // nullable
     int32_t *err;
     int chunk;
+    int span_max;                  // id-range bitmap used when the span is below this
     int persistent;
     int one_item_per_team;         // non-persistent launch: team g takes item begin + g
 };
@@ -428,7 +429,8 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
 
     const int32_t first = T->S[0], last = T->S[d - 1];
     bool bmode = false;
-    if constexpr (Lds::SPAN > 0) bmode = (int64_t)last - (int64_t)first < (int64_t)Lds::SPAN;
+    if constexpr (Lds::SPAN > 0)
+        bmode = (int64_t)last - (int64_t)first < (int64_t)min(Lds::SPAN, a.span_max);
     if (bmode) {
         const int nw = ((last - first) >> 5) + 1;
         for (int i = tlid; i < nw; i += TT) T->bm[i] = 0u;

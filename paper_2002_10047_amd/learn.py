@@ -98,12 +98,12 @@ def train(X, y, steps: int = 3000, batch: int = 4096, lr: float = 3e-3, seed: in
     return tr, hist
 
 
-def save_weights(wb: torch.Tensor, k: int, meta: dict):
+def save_weights(wb: torch.Tensor, k: int, meta: dict, out_dir: str = WEIGHTS_DIR):
     import json
-    os.makedirs(WEIGHTS_DIR, exist_ok=True)
+    os.makedirs(out_dir, exist_ok=True)
     bits = wb.cpu().numpy().view(np.uint16)
-    np.save(os.path.join(WEIGHTS_DIR, f"cost_mlp_k{k}.npy"), bits)
-    with open(os.path.join(WEIGHTS_DIR, f"cost_mlp_k{k}.json"), "w") as f:
+    np.save(os.path.join(out_dir, f"cost_mlp_k{k}.npy"), bits)
+    with open(os.path.join(out_dir, f"cost_mlp_k{k}.json"), "w") as f:
         json.dump(meta, f, indent=1)
 
 
