@@ -142,6 +142,9 @@ typedef struct {
     int bitmap_max_span;   /* membership test of the second level: an id-range bitmap when
                               the members' ids span fewer than this (and the tier's
                               capacity), else a hash; 0 = always hash */
+    int concurrent_tiers;  /* nonzero: the tier kernels of a call run side by side on
+                              library streams forked from and joined back into `stream`
+                              by events (persistent schedules, profiling off) */
     const uint16_t *mlp_weights; /* device bf16 weights for ARB_SCHED_LEARNED (8641) */
     const float *features;       /* device float[n][3] from arb_features, ARB_SCHED_LEARNED */
 } arb_count_opts;
@@ -204,7 +207,7 @@ int arb_profile_read(float *tier_ms, int64_t *tier_items);
 /*
  * Autotuner: coordinate descent (two passes) over the split threshold
  * (split_min_degree, or split_min_cost for ARB_SCHED_LEARNED), persist_blocks_per_cu,
- * chunk_small and bitmap_max_span for this graph and k.  Each candidate runs once to
+ * chunk_small, bitmap_max_span and concurrent_tiers for this graph and k.  Each candidate runs once to
  * warm up and then `trials` times; its time is the fastest run (HIP events on the
  * stream).  Every candidate's total must equal the first one's, else ARB_EMISMATCH.
  * opts: in, the schedule (and weights/features when learned) and starting values;

@@ -56,7 +56,8 @@ class ArbOcsr(ctypes.Structure):
 class ArbCountOpts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("split_min_degree", ctypes.c_int),
                 ("split_min_cost", ctypes.c_float), ("persist_blocks_per_cu", ctypes.c_int),
-                ("chunk_small", ctypes.c_int), ("bitmap_max_span", ctypes.c_int), ("mlp_weights", ctypes.c_void_p),
+                ("chunk_small", ctypes.c_int), ("bitmap_max_span", ctypes.c_int), ("concurrent_tiers", ctypes.c_int),
+                ("mlp_weights", ctypes.c_void_p),
                 ("features", ctypes.c_void_p)]
 
 
@@ -184,7 +185,8 @@ def arb_permute_u64(rank, values, stream=None):
 # ------------------------------------------------------------------ counting
 
 def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost=0.0,
-               persist_blocks_per_cu=8, chunk_small=16, mlp_weights=None, features=None, bitmap_max_span=1 << 30):
+               persist_blocks_per_cu=8, chunk_small=16, mlp_weights=None, features=None, bitmap_max_span=1 << 30,
+               concurrent_tiers=1):
     o = ArbCountOpts()
     _lib.arb_count_default_opts(ctypes.byref(o))
     o.schedule = int(schedule)
@@ -193,6 +195,7 @@ def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost
     o.persist_blocks_per_cu = int(persist_blocks_per_cu)
     o.chunk_small = int(chunk_small)
     o.bitmap_max_span = int(bitmap_max_span)
+    o.concurrent_tiers = int(concurrent_tiers)
     o.mlp_weights = mlp_weights.data_ptr() if mlp_weights is not None else None
     o.features = features.data_ptr() if features is not None else None
     o._keep = (mlp_weights, features)
@@ -202,7 +205,7 @@ def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost
 def opts_dict(o):
     return {"schedule": o.schedule, "split_min_degree": o.split_min_degree, "split_min_cost": o.split_min_cost,
             "persist_blocks_per_cu": o.persist_blocks_per_cu, "chunk_small": o.chunk_small,
-            "bitmap_max_span": o.bitmap_max_span}
+            "bitmap_max_span": o.bitmap_max_span, "concurrent_tiers": o.concurrent_tiers}
 
 
 def arb_autotune(ooff, oidx, k, opts, trials=3, ws=None, stream=None):

@@ -218,6 +218,26 @@ struct Profile {
 };
 static Profile g_prof;
 
+// Streams on which the tier kernels of one call run side by side (fork/join through
+// events from the caller's stream; default priority).  One set per host thread.
+struct TierStreams {
+    bool ready = false;
+    hipStream_t st[kNumTiers];
+    hipEvent_t fork, join[kNumTiers];
+};
+static thread_local TierStreams g_ts;
+
+static int tier_streams_init() {
+    if (g_ts.ready) return ARB_OK;
+    for (int t = 0; t < kNumTiers; ++t) {
+        ARB_HIP(hipStreamCreateWithFlags(&g_ts.st[t], hipStreamNonBlocking));
+        ARB_HIP(hipEventCreateWithFlags(&g_ts.join[t], hipEventDisableTiming));
+    }
+    ARB_HIP(hipEventCreateWithFlags(&g_ts.fork, hipEventDisableTiming));
+    g_ts.ready = true;
+    return ARB_OK;
+}
+
 static int launch_count(int depth, int tier, bool pv, bool instr, const CountArgs &a, unsigned grid, hipStream_t s) {
     switch (depth < 1 ? 1 : depth) {
         case 1: return launch_count_depth1(tier, pv, instr, a, grid, s);
@@ -254,6 +274,7 @@ extern "C" void arb_count_default_opts(arb_count_opts *o) {
     o->persist_blocks_per_cu = 8;
     o->chunk_small = 16;
     o->bitmap_max_span = 1 << 30;
+    o->concurrent_tiers = 1;
     o->mlp_weights = nullptr;
     o->features = nullptr;
 }
@@ -372,6 +393,11 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
         g_prof.seg_dev = w.seg;
         g_prof.stream = s;
     }
+    const bool conc = opts.concurrent_tiers && !prof && !plain;
+    if (conc) {
+        if ((rc = tier_streams_init())) return rc;
+        ARB_HIP(hipEventRecord(g_ts.fork, s));
+    }
     for (int t = kNumTiers - 1; t >= 0; --t) {
         CountArgs a;
         a.off = dg->offsets;
@@ -405,8 +431,17 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
             grid = (unsigned)(cus * per_cu);
         }
         if (prof) ARB_HIP(hipEventRecord(g_prof.ev[2 * t], s));
-        rc = launch_count(k - 3, t, pvm, instr, a, grid, s);
+        hipStream_t ls = s;
+        if (conc) {
+            ls = g_ts.st[t];
+            ARB_HIP(hipStreamWaitEvent(ls, g_ts.fork, 0));
+        }
+        rc = launch_count(k - 3, t, pvm, instr, a, grid, ls);
         if (rc) return rc;
+        if (conc) {
+            ARB_HIP(hipEventRecord(g_ts.join[t], ls));
+            ARB_HIP(hipStreamWaitEvent(s, g_ts.join[t], 0));
+        }
         if (prof) {
             ARB_HIP(hipEventRecord(g_prof.ev[2 * t + 1], s));
             g_prof.launched[t] = true;
@@ -487,8 +522,9 @@ extern "C" int arb_profile_read(float *tier_ms, int64_t *tier_items) {
 namespace {
 
 struct TuneSpace {
-    std::vector<int> split_deg{0, 24, 48, 96, 192};
-    std::vector<float> split_cost{0.f, 10.f, 12.f, 14.f, 16.f, 18.f};
+    std::vector<int> split_deg{0, 32, 64, 128, 256};
+    std::vector<float> split_cost{0.f, 14.f, 17.f, 20.f, 23.f, 26.f};
+    std::vector<int> conc{0, 1};
     std::vector<int> blocks{2, 4, 8};
     std::vector<int> chunk{4, 16, 64};
     std::vector<int> span{0, 1 << 30};
@@ -538,9 +574,10 @@ extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int
     float cur_ms = 0.f;
     if ((rc = measure(cur, &cur_ms))) goto out;
     for (int pass = 0; pass < 2; ++pass) {
-        for (int param = 0; param < 4; ++param) {
+        for (int param = 0; param < 5; ++param) {
             const int nv = param == 0 ? (learned ? (int)sp.split_cost.size() : (int)sp.split_deg.size())
-                         : param == 1 ? (int)sp.blocks.size() : param == 2 ? (int)sp.chunk.size() : (int)sp.span.size();
+                         : param == 1 ? (int)sp.blocks.size() : param == 2 ? (int)sp.chunk.size()
+                         : param == 3 ? (int)sp.span.size() : (int)sp.conc.size();
             for (int i = 0; i < nv; ++i) {
                 arb_count_opts o = cur;
                 if (param == 0) {
@@ -548,7 +585,8 @@ extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int
                     else o.split_min_degree = sp.split_deg[i];
                 } else if (param == 1) o.persist_blocks_per_cu = sp.blocks[i];
                 else if (param == 2) o.chunk_small = sp.chunk[i];
-                else o.bitmap_max_span = sp.span[i];
+                else if (param == 3) o.bitmap_max_span = sp.span[i];
+                else o.concurrent_tiers = sp.conc[i];
                 if (memcmp(&o, &cur, sizeof(o)) == 0) continue;
                 float ms = 0.f;
                 if ((rc = measure(o, &ms))) goto out;
