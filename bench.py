@@ -40,10 +40,14 @@ def parse():
     ap.add_argument("--ks", default="3,4,5")
     ap.add_argument("--eps", type=float, default=1.0)
     ap.add_argument("--schedule", default="learned", choices=["plain", "persistent", "degree", "learned"])
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--no-tune", action="store_true", help="library default options, no autotuning")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner even if options are cached")
+    ap.add_argument("--tune-cache", default="", help="tuned-options cache file (default: the package's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this size once (counter calibration)")
     return ap.parse_args()
 
 
@@ -127,6 +131,45 @@ def cpu_baseline(g, ks, seconds):
                       "sample scaled by its stride, rate = sum(count*stride)/sum(seconds*stride); " + "; ".join(samp)}
 
 
+def copy_calibration(a, torch):
+    """One plain device copy of a known size, for scaling the HBM byte counters."""
+    if not a.copy_calibration_mib:
+        return
+    nb = a.copy_calibration_mib << 20
+    # the copied range is written first and then evicted from the 256 MB Infinity Cache
+    # by writing 1 GiB behind it, so that the copy's reads come from HBM
+    big = torch.ones(nb // 4 + (1 << 28), dtype=torch.float32, device="cuda")
+    src = big[: nb // 4]
+    dst = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {nb} bytes read and {nb} bytes written once")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("count_kernels.h", "count.hip"):
+        with open(os.path.join(ROOT, "paper_2002_10047_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    e = t.get("kernels", {}).get(kernel)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
 def tier_of(d):
     import numpy as np
     b = np.array([64, 128, 256, 384, 512, 768])
@@ -149,6 +192,7 @@ def main():
     from paper_2002_10047_amd import graphgen as gg
 
     ks = [int(x) for x in a.ks.split(",")]
+    arb.arb_profile_enable(True)
     t0 = time.time()
     g = gg.config_graph("c2")
     log(f"graph: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
@@ -166,16 +210,18 @@ def main():
     # ---------------------------------------------------------------- tuning (untimed)
     schedules = {}
     t_tune = time.time()
+    from paper_2002_10047_amd import tuning
+    cache = a.tune_cache or tuning.CACHE
     for name in ("degree", "learned"):
         per_k = {}
         for k in ks:
-            if name == "learned":
-                op = arb.count_opts(schedule=arb.ARB_SCHED_LEARNED, mlp_weights=weights[k], features=feat)
+            if a.no_tune:
+                op = arb.count_opts(schedule=tuning.SCHEDULES[name], mlp_weights=weights[k] if name == "learned" else None,
+                                    features=feat if name == "learned" else None)
             else:
-                op = arb.count_opts(schedule=arb.ARB_SCHED_PERSISTENT)
-            if not a.no_tune:
-                ms = arb.arb_autotune(o["ooff"], o["oidx"], k, op, trials=2, ws=wss[k])
-                log(f"tuned {name} k={k}: {ms:.3f} ms {arb.opts_dict(op)}")
+                op, _ = tuning.tuned_opts(o["ooff"], o["oidx"], k, name, mlp_weights=weights[k] if name == "learned" else None,
+                                          features=feat if name == "learned" else None, ws=wss[k], retune=a.retune,
+                                          path=cache, log=log)
             per_k[k] = op
         schedules[name] = per_k
     schedules["plain"] = {k: arb.count_opts(schedule=arb.ARB_SCHED_PLAIN) for k in ks}
@@ -235,6 +281,7 @@ def main():
         out["learned_gain_vs_plain"] = cmp["plain"] / cmp["learned"]
         opts = schedules[main_name][ks[0]]
     if a.no_extras:
+        copy_calibration(a, torch)
         print(json.dumps(out), flush=True)
         return
 
@@ -261,56 +308,57 @@ def main():
         ", ".join(f"k={k}: {v['count_s'] * 1e3:.3f} ms" for k, v in per_k.items()))
 
     # ---------------------------------------------------------------- roofline
-    arb.arb_profile_enable(True)
-    tiers = {}
-    for k in ks:
-        arb.arb_count_async(o["ooff"], o["oidx"], k, total=totals[k], opts=schedules[main_name][k], ws=wss[k])
-        ms, items = arb.arb_profile_read()
-        tiers[k] = (ms, items)
+    # every counting-kernel launch of this run was timed with HIP events on its own
+    # stream; a kernel symbol k_count<W, depth, 0, 0> serves tier W and depth max(1, k-3)
+    prof = [e for e in arb.arb_profile_read() if not e["per_vertex"] and not e["instrumented"]]
     arb.arb_profile_enable(False)
     d, W, gather, nodes = algorithmic_units(arb, o, ks, np)
-    best = None
-    for k in ks:
-        ms, items = tiers[k]
+    tw = [2, 4, 8, 12, 16, 24]
+    per_sym = {}
+    for e in prof:
+        k, ti = e["k"], e["tier"]
         live = d >= k - 1
-        t = tier_of(d)
-        for ti in range(6):
-            if ms[ti] <= 0:
-                continue
-            sel = live & (t == ti)
-            hbm_bytes = float(4 * (d[sel] + 4 * d[sel] + gather[sel]).sum() + 16 * sel.sum())
-            if k >= 4:
-                ck2 = nodes[k][sel] - nodes[k - 1][sel]          # c_{k-2}(v)
-                deep = nodes[k][sel] - d[sel]                    # sum_{j=2}^{k-2} c_j(v)
-                # every node of depth >= 2 ANDs W words; nodes of depth k-2 also popcount them
-                alu_ops = float((W[sel] * (deep + ck2)).sum())
-            else:
-                alu_ops = 0.0
-            sec = ms[ti] / 1e3
-            hbm = hbm_bytes / sec / 1e9
-            alu = alu_ops / sec / 1e12
-            fr_h = hbm / PEAK_HBM_GBS
-            fr_a = alu / PEAK_ALU_TOPS
-            cand = dict(k=k, tier=ti, ms=ms[ti], items=int(items[ti]), hbm_GBs=hbm, alu_Tops=alu,
-                        hbm_bytes=hbm_bytes, alu_ops=alu_ops, frac_hbm=fr_h, frac_alu=fr_a)
-            if best is None or ms[ti] > best["ms"]:
-                best = cand
-            log(f"  k={k} tier {ti}: {ms[ti]:.3f} ms, {items[ti]} items, algorithmic {hbm:.0f} GB/s "
-                f"({fr_h:.2%} of HBM), {alu:.2f} Tops ({fr_a:.2%} of ALU)")
+        sel = live & (tier_of(d) == ti)
+        hbm_bytes = float(4 * (d[sel] + 4 * d[sel] + gather[sel]).sum() + 16 * sel.sum())
+        alu_ops = 0.0
+        if k >= 4:
+            ck2 = nodes[k][sel] - nodes[k - 1][sel]          # c_{k-2}(v)
+            deep = nodes[k][sel] - d[sel]                    # sum_{j=2}^{k-2} c_j(v)
+            # every node of depth >= 2 ANDs W words; nodes of depth k-2 also popcount them
+            alu_ops = float((W[sel] * (deep + ck2)).sum())
+        sym = f"k_count<{tw[ti]},{max(1, k - 3)},0,0>"
+        s_ = per_sym.setdefault(sym, dict(launches=0, ms=0.0, hbm=0.0, alu=0.0, parts=[]))
+        s_["launches"] += e["launches"]
+        s_["ms"] += e["total_ms"]
+        s_["hbm"] += e["launches"] * hbm_bytes
+        s_["alu"] += e["launches"] * alu_ops
+        s_["parts"].append(f"k={k}: {e['launches']} launches, {e['total_ms'] / e['launches']:.3f} ms avg")
+    best = None
+    for sym, v in sorted(per_sym.items()):
+        sec = v["ms"] / 1e3
+        hbm = v["hbm"] / sec / 1e9
+        alu = v["alu"] / sec / 1e12
+        log(f"  {sym}: {v['launches']} launches, avg {v['ms'] / v['launches']:.3f} ms ({'; '.join(v['parts'])}), "
+            f"algorithmic {hbm:.0f} GB/s ({hbm / PEAK_HBM_GBS:.2%} of HBM), {alu:.2f} Tops ({alu / PEAK_ALU_TOPS:.2%} of ALU)")
+        if best is None or v["ms"] > best[1]["ms"]:
+            best = (sym, v, hbm, alu)
     if best:
-        if best["frac_alu"] >= best["frac_hbm"]:
-            out["roofline"] = {"bound": "alu", "achieved": best["alu_Tops"], "peak": PEAK_ALU_TOPS,
-                               "unit": "Tops/s", "frac": best["frac_alu"], "traffic": None}
+        sym, v, hbm, alu = best
+        fr_h, fr_a = hbm / PEAK_HBM_GBS, alu / PEAK_ALU_TOPS
+        if fr_a >= fr_h:
+            out["roofline"] = {"bound": "alu", "achieved": alu, "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "frac": fr_a}
         else:
-            out["roofline"] = {"bound": "hbm", "achieved": best["hbm_GBs"], "peak": PEAK_HBM_GBS,
-                               "unit": "GB/s", "frac": best["frac_hbm"], "traffic": None}
-        out["roofline"]["kernel"] = f"k_count tier {best['tier']} (k={best['k']})"
-        out["roofline"]["launch_ms"] = best["ms"]
-        out["roofline"]["items"] = best["items"]
+            out["roofline"] = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": fr_h}
+        out["roofline"]["traffic"] = measured_traffic(sym)
+        out["roofline"]["kernel"] = sym
+        out["roofline"]["launches"] = v["launches"]
+        out["roofline"]["launch_ms"] = v["ms"] / v["launches"]
+        out["roofline"]["algorithmic_per_launch"] = (v["alu"] if fr_a >= fr_h else v["hbm"]) / v["launches"]
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, ks, a.cpu_seconds)
+    copy_calibration(a, torch)
     print(json.dumps(out), flush=True)
 
 

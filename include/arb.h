@@ -194,15 +194,18 @@ int arb_segment_sum_u64(const uint64_t *in, const int64_t *offsets, int64_t G, u
 uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex,
                    const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
-/* Per-launch timing of the counting kernels.  While enabled, every arb_count /
- * arb_count_async call records a HIP event before and after each of its
- * ARB_NUM_TIERS tier kernels (tier t holds items whose candidate set fits 64, 128,
- * 256, 384, 512, 768 local vertices).  arb_profile_read waits for the last profiled
- * call's stream and returns per tier the kernel time in ms (0 if not launched) and its
- * number of work items (host arrays of ARB_NUM_TIERS entries).  Synchronises. */
+/* Launch timing of the counting kernels.  While enabled, each tier-kernel launch of
+ * arb_count / arb_count_async / arb_autotune is bracketed by two HIP events on the
+ * stream it runs on (tier t holds items whose candidate set fits 64, 128, 256, 384,
+ * 512, 768 local vertices).  arb_profile_enable(1) clears the totals.  arb_profile_read
+ * waits for pending events and fills, for each (tier, k, per-vertex, instrumented)
+ * seen, the number of launches and their summed duration in ms (host arrays of
+ * max_entries); it returns the number of entries (which may exceed max_entries), or
+ * -1 on error.  Not thread-safe; synchronises. */
 #define ARB_NUM_TIERS 6
 int arb_profile_enable(int on);
-int arb_profile_read(float *tier_ms, int64_t *tier_items);
+int arb_profile_read(int max_entries, int32_t *tier, int32_t *k, int32_t *per_vertex,
+                     int32_t *instrumented, int64_t *launches, double *total_ms);
 
 /*
  * Autotuner: coordinate descent (two passes) over the split threshold

@@ -83,7 +83,7 @@ _sigs = {
     "arb_to_bf16": ([P, P, I64, P], I32),
     "arb_autotune": ([P, I32, P, I32, P, P, SZ, P], I32),
     "arb_profile_enable": ([I32], I32),
-    "arb_profile_read": ([P, P], I32),
+    "arb_profile_read": ([I32, P, P, P, P, P, P], I32),
     "arb_last_error": ([], I32),
     "arb_error_string": ([I32], ctypes.c_char_p),
 }
@@ -263,21 +263,18 @@ def arb_profile_enable(on: bool = True):
     _check(_lib.arb_profile_enable(int(bool(on))), "arb_profile_enable")
 
 
-def arb_profile_read():
-    """(tier_ms float[6], tier_items int64[6]) of the last profiled count call."""
-    ms = (ctypes.c_float * 6)()
-    items = (ctypes.c_int64 * 6)()
-    _check(_lib.arb_profile_read(ms, items), "arb_profile_read")
-    return np.array(ms[:], np.float64), np.array(items[:], np.int64)
-
-
-def arb_segment_sum_u64(values, offsets, stream=None):
-    """Per-segment sums of a device uint64 (int64-typed) tensor; offsets: device int64[G+1]."""
-    G = offsets.numel() - 1
-    out = torch.empty(max(G, 1), dtype=torch.int64, device=values.device)
-    _check(_lib.arb_segment_sum_u64(_ptr(values), _ptr(offsets), G, _ptr(out), _stream(stream)),
-           "arb_segment_sum_u64")
-    return out[:G]
+def arb_profile_read(max_entries: int = 256):
+    """List of dicts (tier, k, per_vertex, instrumented, launches, total_ms) accumulated
+    since arb_profile_enable(True)."""
+    T = (ctypes.c_int32 * max_entries)
+    tier, k, pv, ins = T(), T(), T(), T()
+    la = (ctypes.c_int64 * max_entries)()
+    ms = (ctypes.c_double * max_entries)()
+    nent = _lib.arb_profile_read(max_entries, tier, k, pv, ins, la, ms)
+    if nent < 0:
+        raise ArbError(arb_last_error(), "arb_profile_read")
+    return [dict(tier=tier[i], k=k[i], per_vertex=pv[i], instrumented=ins[i], launches=la[i], total_ms=ms[i])
+            for i in range(min(nent, max_entries))]
 
 
 # ------------------------------------------------------------------ learned schedule

@@ -206,17 +206,55 @@ static size_t carve_count(Carver &c, int64_t n, int64_t m, CountWs *w) {
 // learned cost (mlp.hip): predicted log2(1 + work) per root
 int learned_cost(const arb_ocsr *dg, const uint16_t *w, const float *feat, float *cost, hipStream_t s);
 
-// Optional per-tier timing: events recorded around each tier launch of the last
-// profiled call, plus the tier item ranges.
+// Optional launch timing: while enabled, every counting-kernel launch is bracketed by
+// two HIP events on the stream it runs on; arb_profile_read folds the pending pairs into
+// per-(tier, k, per-vertex, instrumented) totals.
+struct ProfKey {
+    int tier, k, pv, instr;
+    bool operator==(const ProfKey &o) const { return tier == o.tier && k == o.k && pv == o.pv && instr == o.instr; }
+};
+struct ProfPending {
+    ProfKey key;
+    hipEvent_t a, b;
+};
+struct ProfTotal {
+    ProfKey key;
+    int64_t launches;
+    double ms;
+};
 struct Profile {
     bool enabled = false;
-    bool created = false;
-    hipEvent_t ev[2 * kNumTiers];
-    bool launched[kNumTiers];
-    const int64_t *seg_dev = nullptr;
-    hipStream_t stream = nullptr;
+    std::vector<ProfPending> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<ProfTotal> totals;
 };
 static Profile g_prof;
+
+static int prof_event(hipEvent_t *e) {
+    if (!g_prof.pool.empty()) {
+        *e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return ARB_OK;
+    }
+    ARB_HIP(hipEventCreate(e));
+    return ARB_OK;
+}
+
+static int prof_fold() {
+    for (auto &p : g_prof.pending) {
+        ARB_HIP(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        ARB_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        bool found = false;
+        for (auto &t : g_prof.totals)
+            if (t.key == p.key) { t.launches += 1; t.ms += ms; found = true; break; }
+        if (!found) g_prof.totals.push_back(ProfTotal{p.key, 1, (double)ms});
+        g_prof.pool.push_back(p.a);
+        g_prof.pool.push_back(p.b);
+    }
+    g_prof.pending.clear();
+    return ARB_OK;
+}
 
 // Streams on which the tier kernels of one call run side by side (fork/join through
 // events from the caller's stream; default priority).  One set per host thread.
@@ -384,16 +422,8 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     }
     const int cus = device_cus();
     const bool prof = g_prof.enabled;
-    if (prof) {
-        if (!g_prof.created) {
-            for (int e = 0; e < 2 * kNumTiers; ++e) ARB_HIP(hipEventCreate(&g_prof.ev[e]));
-            g_prof.created = true;
-        }
-        for (int t = 0; t < kNumTiers; ++t) g_prof.launched[t] = false;
-        g_prof.seg_dev = w.seg;
-        g_prof.stream = s;
-    }
-    const bool conc = opts.concurrent_tiers && !prof && !plain;
+    if (prof && g_prof.pending.size() > 2048 && (rc = prof_fold())) return rc;
+    const bool conc = opts.concurrent_tiers && !plain;
     if (conc) {
         if ((rc = tier_streams_init())) return rc;
         ARB_HIP(hipEventRecord(g_ts.fork, s));
@@ -430,21 +460,25 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
             if (per_cu < 1) per_cu = 1;
             grid = (unsigned)(cus * per_cu);
         }
-        if (prof) ARB_HIP(hipEventRecord(g_prof.ev[2 * t], s));
         hipStream_t ls = s;
         if (conc) {
             ls = g_ts.st[t];
             ARB_HIP(hipStreamWaitEvent(ls, g_ts.fork, 0));
         }
+        ProfPending pp{ProfKey{t, k, pvm ? 1 : 0, instr ? 1 : 0}, nullptr, nullptr};
+        if (prof) {
+            if ((rc = prof_event(&pp.a)) || (rc = prof_event(&pp.b))) return rc;
+            ARB_HIP(hipEventRecord(pp.a, ls));
+        }
         rc = launch_count(k - 3, t, pvm, instr, a, grid, ls);
         if (rc) return rc;
+        if (prof) {
+            ARB_HIP(hipEventRecord(pp.b, ls));
+            g_prof.pending.push_back(pp);
+        }
         if (conc) {
             ARB_HIP(hipEventRecord(g_ts.join[t], ls));
             ARB_HIP(hipStreamWaitEvent(s, g_ts.join[t], 0));
-        }
-        if (prof) {
-            ARB_HIP(hipEventRecord(g_prof.ev[2 * t + 1], s));
-            g_prof.launched[t] = true;
         }
     }
     k_finish<<<1, 64, 0, s>>>(w.err, total);
@@ -486,35 +520,41 @@ extern "C" uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex, c
 }
 
 extern "C" int arb_profile_enable(int on) {
+    int rc = ARB_OK;
+    if (on) {
+        rc = prof_fold();
+        g_prof.totals.clear();
+    } else {
+        rc = prof_fold();
+    }
     g_prof.enabled = on != 0;
-    set_error(ARB_OK);
-    return ARB_OK;
+    set_error(rc);
+    return rc;
 }
 
-extern "C" int arb_profile_read(float *tier_ms, int64_t *tier_items) {
-    if (!tier_ms || !tier_items) { set_error(ARB_EINVAL); return ARB_EINVAL; }
-    int64_t seg[16] = {0};
-    if (g_prof.seg_dev) {
-        if (hipStreamSynchronize(g_prof.stream) != hipSuccess ||
-            hipMemcpy(seg, g_prof.seg_dev, sizeof(int64_t) * 9, hipMemcpyDeviceToHost) != hipSuccess) {
-            set_error(ARB_EHIP);
-            return ARB_EHIP;
-        }
+extern "C" int arb_profile_read(int max_entries, int32_t *tier, int32_t *k, int32_t *per_vertex,
+                                int32_t *instrumented, int64_t *launches, double *total_ms) {
+    if (max_entries < 0 || (max_entries > 0 && (!tier || !k || !per_vertex || !instrumented || !launches ||
+                                                !total_ms))) {
+        set_error(ARB_EINVAL);
+        return -1;
     }
-    for (int t = 0; t < kNumTiers; ++t) {
-        tier_ms[t] = 0.f;
-        tier_items[t] = seg[t + 1] - seg[t];
-        if (g_prof.created && g_prof.launched[t]) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, g_prof.ev[2 * t], g_prof.ev[2 * t + 1]) != hipSuccess) {
-                set_error(ARB_EHIP);
-                return ARB_EHIP;
-            }
-            tier_ms[t] = ms;
+    int rc = prof_fold();
+    if (rc) { set_error(rc); return -1; }
+    int nout = 0;
+    for (auto &t : g_prof.totals) {
+        if (nout < max_entries) {
+            tier[nout] = t.key.tier;
+            k[nout] = t.key.k;
+            per_vertex[nout] = t.key.pv;
+            instrumented[nout] = t.key.instr;
+            launches[nout] = t.launches;
+            total_ms[nout] = t.ms;
         }
+        ++nout;
     }
     set_error(ARB_OK);
-    return ARB_OK;
+    return nout;
 }
 
 // ------------------------------------------------------------------ autotuner
