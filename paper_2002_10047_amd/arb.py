@@ -131,6 +131,26 @@ def u64_numpy(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy().view(np.uint64)
 
 
+# ------------------------------------------------------------------ workspace sizes
+
+def arb_orient_workspace(n: int, nnz: int) -> int:
+    return int(_lib.arb_orient_workspace(int(n), int(nnz)))
+
+
+def arb_count_workspace(n: int, m: int, k: int) -> int:
+    return int(_lib.arb_count_workspace(int(n), int(m), int(k)))
+
+
+def arb_mlp_workspace(rows: int) -> int:
+    return int(_lib.arb_mlp_workspace(int(rows)))
+
+
+def arb_count_default_opts():
+    o = ArbCountOpts()
+    _lib.arb_count_default_opts(ctypes.byref(o))
+    return o
+
+
 # ------------------------------------------------------------------ orientation
 
 def arb_orient(offsets: torch.Tensor, indices: torch.Tensor, eps: float = 1.0, validate: bool = False,
@@ -275,6 +295,15 @@ def arb_profile_read(max_entries: int = 256):
         raise ArbError(arb_last_error(), "arb_profile_read")
     return [dict(tier=tier[i], k=k[i], per_vertex=pv[i], instrumented=ins[i], launches=la[i], total_ms=ms[i])
             for i in range(min(nent, max_entries))]
+
+
+def arb_segment_sum_u64(values, offsets, stream=None):
+    """Per-segment sums of a device uint64 (int64-typed) tensor; offsets: device int64[G+1]."""
+    G = offsets.numel() - 1
+    out = torch.empty(max(G, 1), dtype=torch.int64, device=values.device)
+    _check(_lib.arb_segment_sum_u64(_ptr(values), _ptr(offsets), G, _ptr(out), _stream(stream)),
+           "arb_segment_sum_u64")
+    return out[:G]
 
 
 # ------------------------------------------------------------------ learned schedule

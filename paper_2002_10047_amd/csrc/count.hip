@@ -433,6 +433,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
         a.off = dg->offsets;
         a.idx = dg->indices;
         a.n = n;
+        a.m = m;
         a.k = k;
         a.item_root = w.iroot;
         a.item_child = w.ichild;

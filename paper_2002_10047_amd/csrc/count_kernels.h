@@ -60,6 +60,15 @@ constexpr int pow2_at_least(int x) {
     return p;
 }
 
+// One list of the second level as a span of the wave's concatenated element stream:
+// stream positions [end - len, end) map to idx[q + delta]; row = local id of its vertex.
+struct ListEnt {
+    int64_t delta;
+    int64_t end;
+    int32_t row;
+    int32_t pad;
+};
+
 template <int W, bool PV>
 struct TeamLds {
     static constexpr int D = 32 * W;             // capacity of S
@@ -77,6 +86,7 @@ struct TeamLds {
     uint32_t rows[D * RS];
     unsigned long long cnt[PV ? D : 1];
     uint32_t ring[TW][RING];
+    ListEnt lt[TW][64];     // second level: the wave's current 64 lists
     unsigned long long red[TW];
     int d;
     int pop;
@@ -196,6 +206,7 @@ struct CountArgs {
     const int64_t *off;
     const int32_t *idx;
     int64_t n;
+    int64_t m;
     int k;
     const int32_t *item_root;
     const int32_t *item_child;
@@ -360,6 +371,88 @@ __device__ __forceinline__ Acc do_pair(AS3<Lds> *T, uint32_t p, int need) {
     return out;
 }
 
+// ------------------------------------------------------------------ second level
+
+constexpr int kGatherUnroll = 8;   // independent 4-byte loads in flight per lane
+
+// Second level of the recursion: for the lists N+(S[i]), i = g0, g0 + gstep, ... < d,
+// keep the entries that are members of S.  A wave takes 64 lists at a time, concatenates
+// them into one element stream and consumes it 64 * kGatherUnroll entries per step, each
+// lane walking its own cursor through the list table in LDS, so that short and long
+// lists alike keep kGatherUnroll loads per lane in flight.
+template <int W, bool PV, class Lds>
+__device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, int d, int need, int g0, int gstep,
+                                             int32_t first, int32_t last, bool bmode, int wv, int lane,
+                                             unsigned long long &mine, unsigned long long &words) {
+    AS3<ListEnt> *lt = T->lt[wv];
+    const int nl = g0 < d ? (d - g0 + gstep - 1) / gstep : 0;
+    for (int gb = 0; gb < nl; gb += 64) {
+        const int t = gb + lane;
+        int64_t s = 0, e = 0;
+        int row = 0;
+        if (t < nl) {
+            row = g0 + gstep * t;
+            const int32_t u = T->S[row];
+            s = a.off[u];
+            e = a.off[u + 1];
+        }
+        const int64_t len = e - s;
+        words += (unsigned long long)len;
+        int64_t end = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(end, o, 64);
+            if (lane >= o) end += y;
+        }
+        const int64_t total = __shfl(end, 63, 64);
+        lt[lane].delta = s - (end - len);
+        lt[lane].end = end;
+        lt[lane].row = row;
+        wave_fence();
+        int c = 0;                                  // this lane's cursor into the table
+        int64_t c_end = lt[0].end;
+        int64_t c_delta = lt[0].delta;
+        int c_row = lt[0].row;
+        for (int64_t base = 0; base < total; base += 64 * kGatherUnroll) {
+            int32_t w[kGatherUnroll];
+            int r[kGatherUnroll];
+#pragma unroll
+            for (int q = 0; q < kGatherUnroll; ++q) {
+                const int64_t pos = base + 64 * q + lane;
+                w[q] = 0x7fffffff;
+                r[q] = 0;
+                if (pos < total) {
+                    while (pos >= c_end) {
+                        ++c;
+                        c_end = lt[c].end;
+                        c_delta = lt[c].delta;
+                        c_row = lt[c].row;
+                    }
+                    w[q] = a.idx[pos + c_delta];
+                    r[q] = c_row;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kGatherUnroll; ++q) {
+                const int j = member_find(T, w[q], first, last, bmode);
+                if (j < 0) continue;
+                const int i = r[q];
+                if (need == 2) {
+                    mine += 1;
+                    if constexpr (PV) {
+                        lds_add(&T->cnt[j], 1ull);
+                        lds_add(&T->cnt[i], 1ull);
+                    }
+                } else {
+                    lds_or(&T->rows[i * Lds::RS + (j >> 5)], 1u << (j & 31));
+                    if constexpr (PV) lds_or(&T->rows[j * Lds::RS + (i >> 5)], 1u << (i & 31));
+                }
+            }
+        }
+        wave_fence();                               // table reused by the next 64 lists
+    }
+}
+
 // ------------------------------------------------------------------ one work item
 
 template <int W, int LMAX, bool PV, bool INSTR>
@@ -462,47 +555,12 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
         if constexpr (PV)
             for (int i = tlid; i < d; i += TT) T->cnt[i] = 1ull;
     } else {
-        // second level: read N+(u) for each member u (four 64-lane chunks in flight per
-        // wave) and keep the entries that are members; rows ascend, so a list is left as
-        // soon as it passes the largest member
-        // k-1 = 2 (no bit rows): the gather is the whole work, so parts split its rows
+        // second level; with k-1 = 2 (no bit rows) the gather is the whole work, so parts
+        // split its lists
         const int g0 = need == 2 ? part + P * wv : wv, gstep = need == 2 ? P * TW : TW;
-        for (int i = g0; i < d; i += gstep) {
-            const int32_t u = T->S[i];
-            const int64_t s = a.off[u], e = a.off[u + 1];
-            if constexpr (INSTR) {
-                if (lane == 0) gather += (unsigned long long)(e - s);
-            }
-            unsigned rowcnt = 0;
-            for (int64_t b = s; b < e; b += 256) {
-                int32_t wc[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int64_t p = b + 64 * c + lane;
-                    wc[c] = p < e ? a.idx[p] : 0x7fffffff;
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int j = member_find(T, wc[c], first, last, bmode);
-                    const bool hit = j >= 0;
-                    if (need == 2) {
-                        if (hit) mine += 1;
-                        if constexpr (PV) {
-                            rowcnt += (unsigned)__popcll(__ballot(hit));
-                            if (hit) lds_add(&T->cnt[j], 1ull);
-                        }
-                    } else if (hit) {
-                        lds_or(&T->rows[i * Lds::RS + (j >> 5)], 1u << (j & 31));
-                        if constexpr (PV) lds_or(&T->rows[j * Lds::RS + (i >> 5)], 1u << (i & 31));
-                    }
-                }
-                if (__shfl(wc[3], 63, 64) > last) break;
-            }
-            if constexpr (PV) {
-                if (need == 2 && lane == 0 && rowcnt)
-                    lds_add(&T->cnt[i], (unsigned long long)rowcnt);
-            }
-        }
+        unsigned long long words = 0;
+        gather_lists<W, PV, Lds>(T, a, d, need, g0, gstep, first, last, bmode, wv, lane, mine, words);
+        if constexpr (INSTR) gather += words;
         if constexpr (INSTR) {
             if (tlid == 0) nodes += (unsigned long long)d;     // depth-1 nodes
         }

@@ -54,3 +54,9 @@ def test_invalid_arguments_rejected_without_device():
     assert lib.arb_orient(None, 1.0, 0, None, None, None, None, None, None, 0, None) == 1
     lib.arb_last_error.restype = ctypes.c_int
     assert lib.arb_last_error() == 1
+
+
+def test_binding_wraps_every_declared_function():
+    src = open(os.path.join(ROOT, "paper_2002_10047_amd", "arb.py")).read()
+    missing = [n for n in declared() if f"def {n}(" not in src]
+    assert not missing, missing
