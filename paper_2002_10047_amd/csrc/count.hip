@@ -455,7 +455,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
             if (cnt <= 0) continue;
             grid = (unsigned)((cnt + tpb - 1) / tpb);
         } else {
-            const size_t lds = tier_block_lds(t, pvm);
+            const size_t lds = tier_block_lds(t, pvm, k - 3 < 1 ? 1 : k - 3);
             int per_cu = (int)((160 * 1024) / (lds > 0 ? lds : 1));
             if (per_cu > opts.persist_blocks_per_cu) per_cu = opts.persist_blocks_per_cu;
             if (per_cu < 1) per_cu = 1;

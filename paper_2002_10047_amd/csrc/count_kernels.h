@@ -25,6 +25,8 @@
 #pragma once
 #include "common.h"
 
+#include <type_traits>
+
 namespace arb {
 
 // ------------------------------------------------------------------ tiers
@@ -32,13 +34,21 @@ namespace arb {
 // local candidate-set capacity per tier: 32 * W (W 32-bit words per bit row)
 // TW waves per team, TPB teams per block, SPAN: id-range bitmap capacity (bits) used for
 // the membership test when the members' ids span fewer than SPAN values (else a hash).
-template <int W> struct TierCfg;
-template <> struct TierCfg<2>  { static constexpr int TW = 1, TPB = 4, SPAN = 0; };
-template <> struct TierCfg<4>  { static constexpr int TW = 4, TPB = 1, SPAN = 1 << 16; };
-template <> struct TierCfg<8>  { static constexpr int TW = 4, TPB = 1, SPAN = 1 << 15; };
-template <> struct TierCfg<12> { static constexpr int TW = 8, TPB = 1, SPAN = 1 << 15; };
-template <> struct TierCfg<16> { static constexpr int TW = 8, TPB = 1, SPAN = 1 << 15; };
-template <> struct TierCfg<24> { static constexpr int TW = 8, TPB = 1, SPAN = 1 << 14; };
+// The two largest tiers run 16-wave teams when counting totals at recursion depth <= 2
+// (one 1024-lane block per CU keeps four waves on every SIMD within 128 VGPRs); deeper
+// walks and the per-vertex variants need more registers per lane and keep 8-wave teams.
+template <int W, bool PV, int LMAX> struct TierCfg {
+    static_assert(W <= 32, "the pair phase scans one row's words within 32 lanes");
+    static constexpr bool wide = !PV && LMAX <= 2;
+    static constexpr int TW = W == 2 ? 1 : (W <= 8 ? 4 : (wide && W >= 16 ? 16 : 8));
+    static constexpr int TPB = W == 2 ? 4 : 1;
+    static constexpr int SPAN = W == 2 ? 0 : (W == 4 ? 1 << 16 : (W <= 16 ? 1 << 15 : 1 << 14));
+};
+
+template <int W, bool PV, int LMAX>
+constexpr int tier_threads() {
+    return 64 * TierCfg<W, PV, LMAX>::TW * TierCfg<W, PV, LMAX>::TPB;
+}
 
 constexpr int kNumTiers = 6;
 constexpr int kTierW[kNumTiers] = {2, 4, 8, 12, 16, 24};
@@ -69,15 +79,21 @@ struct ListEnt {
     int32_t pad;
 };
 
-template <int W, bool PV>
+template <int W, bool PV, int TW_>
 struct TeamLds {
     static constexpr int D = 32 * W;             // capacity of S
     static constexpr int RS = W + 1;             // row stride in words (odd: spreads banks)
     static constexpr int HS = pow2_at_least(D <= 128 ? 4 * D : 2 * D);
     static constexpr int HB = __builtin_ctz(HS);
-    static constexpr int TW = TierCfg<W>::TW;
+    static constexpr int TW = TW_;
+    // per-wave pair ring (power of two): holds a whole row on top of a partial chunk.  An
+    // entry is (x << 16 | y), or in the 768-tier (slot << 10 | y) with x kept in a 64-slot
+    // table of the wave's recent non-empty rows: fewer than 64 entries are ever left over
+    // from earlier rows, so a slot is reused only after its entries were taken
     static constexpr int RING = pow2_at_least(D + 64);
-    static constexpr int SPAN = TierCfg<W>::SPAN;
+    static constexpr bool CR = W == 24;
+    using RingT = typename std::conditional<CR, uint16_t, uint32_t>::type;
+    static constexpr int SPAN = TierCfg<W, PV, 1>::SPAN;
     static constexpr int SW = SPAN > 0 ? SPAN / 32 : 1;
     int32_t S[D];
     unsigned long long H[HS];
@@ -85,11 +101,15 @@ struct TeamLds {
     uint16_t pre[SW];       // local id of the first member in each bitmap word
     uint32_t rows[D * RS];
     unsigned long long cnt[PV ? D : 1];
-    uint32_t ring[TW][RING];
-    ListEnt lt[TW][64];     // second level: the wave's current 64 lists
+    union {
+        RingT ring[TW][RING];       // pair phase
+        ListEnt lt[TW][64];         // second level: the wave's current 64 lists
+    } q;
+    uint16_t xs[CR ? TW : 1][64];   // compact ring: row of each slot
     unsigned long long red[TW];
     int d;
     int pop;
+    int next;               // next row to claim in the pair phase
 };
 
 // Every LDS access goes through pointers in the LDS address space, so that helpers the
@@ -262,17 +282,25 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
     }
     if constexpr (L == 2 && !PV) {
         // leaf level on upper rows: row z has no bits below z, so the AND starts at z's word
+// two members per step, so that the second row's LDS reads overlap the first's
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             uint32_t bits = J.w[w];
             while (bits) {
-                const int z = w * 32 + __ffs(bits) - 1;
+                const int z1 = w * 32 + __ffs(bits) - 1;
                 bits &= bits - 1;
-                const AS3<uint32_t> *rz = &T->rows[z * Lds::RS];
-                unsigned c = 0;
+                const bool two = bits != 0;
+                const int z2 = two ? w * 32 + __ffs(bits) - 1 : z1;
+                bits &= bits - 1;
+                const AS3<uint32_t> *r1 = &T->rows[z1 * Lds::RS];
+                const AS3<uint32_t> *r2 = &T->rows[z2 * Lds::RS];
+                unsigned c1 = 0, c2 = 0;
 #pragma unroll
-                for (int v = w; v < W; ++v) c += __popc(J.w[v] & rz[v]);
-                out.c += c;
+                for (int v = w; v < W; ++v) {
+                    c1 += __popc(J.w[v] & r1[v]);
+                    c2 += __popc(J.w[v] & r2[v]);
+                }
+                out.c += c1 + (two ? c2 : 0u);
             }
         }
         return out;
@@ -331,8 +359,7 @@ static_assert(ARB_MAX_K - 3 <= 7, "dfs_dispatch covers L up to ARB_MAX_K - 3");
 // One pair (x, y) of the induced subgraph, x < y, both chosen: count the cliques that
 // extend it with `need` more vertices from S (need >= 1); .nodes as in dfs.
 template <int W, int LMAX, bool PV, bool INSTR, class Lds>
-__device__ __forceinline__ Acc do_pair(AS3<Lds> *T, uint32_t p, int need) {
-    const int x = (int)(p >> 16), y = (int)(p & 0xffffu);
+__device__ __forceinline__ Acc do_pair(AS3<Lds> *T, int x, int y, int need) {
     const AS3<uint32_t> *rx = &T->rows[x * Lds::RS];
     const AS3<uint32_t> *ry = &T->rows[y * Lds::RS];
     Acc out{0ull, INSTR ? 1ull : 0ull};
@@ -384,7 +411,7 @@ template <int W, bool PV, class Lds>
 __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, int d, int need, int g0, int gstep,
                                              int32_t first, int32_t last, bool bmode, int wv, int lane,
                                              unsigned long long &mine, unsigned long long &words) {
-    AS3<ListEnt> *lt = T->lt[wv];
+    AS3<ListEnt> *lt = T->q.lt[wv];
     const int nl = g0 < d ? (d - g0 + gstep - 1) / gstep : 0;
     for (int gb = 0; gb < nl; gb += 64) {
         const int t = gb + lane;
@@ -456,10 +483,12 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
 // ------------------------------------------------------------------ one work item
 
 template <int W, int LMAX, bool PV, bool INSTR>
-__device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *T, const CountArgs a, int32_t root,
+__device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, TierCfg<W, PV, LMAX>::TW>> *T,
+                                                             const CountArgs a, int32_t root,
                                                              int32_t child, int tlid) {
-    using Lds = TeamLds<W, PV>;
-    constexpr int TW = TierCfg<W>::TW, TPB = TierCfg<W>::TPB;
+    using Cfg = TierCfg<W, PV, LMAX>;
+    constexpr int TW = Cfg::TW, TPB = Cfg::TPB;
+    using Lds = TeamLds<W, PV, TW>;
     constexpr int TT = 64 * TW;
     const int lane = tlid & 63, wv = tlid >> 6;
     const uint64_t below = lanes_below_mask();
@@ -532,6 +561,7 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
     }
     if (need >= 3)
         for (int i = tlid; i < d * Lds::RS; i += TT) T->rows[i] = 0u;
+    if (tlid == 0) T->next = TW;
     if constexpr (PV)
         for (int i = tlid; i < d; i += TT) T->cnt[i] = 0ull;
     team_sync<TW, TPB>();
@@ -566,51 +596,81 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
         }
         if (need >= 3) {
             team_sync<TW, TPB>();
-            // pairs (x, y), y > x adjacent, spread over the lanes through the wave's ring
-            AS3<uint32_t> *ring = T->ring[wv];
-            unsigned head = 0, tail = 0;
+            // pairs (x, y), y > x adjacent, spread over the lanes through the wave's ring.  When subtrees lie below the
+            // pairs (pneed >= 2) the waves of a team claim rows in ascending order (largest
+            // rows first) from a team counter, one claim ahead; otherwise rows are dealt
+            // round-robin
+            using RingT = typename Lds::RingT;
+            AS3<RingT> *ring = T->q.ring[wv];
+            unsigned head = 0, tail = 0;          // ring positions [head, tail) not yet taken
             const int pneed = need - 2;
-            for (int x = part + P * wv; x < d; x += P * TW) {
+            unsigned slot = 0;
+            auto take = [&](uint32_t p) {
+                int px, py;
+                if constexpr (Lds::CR) {
+                    px = T->xs[wv][p >> 10];
+                    py = (int)(p & 1023u);
+                } else {
+                    px = (int)(p >> 16);
+                    py = (int)(p & 0xffffu);
+                }
+                const Acc r = do_pair<W, LMAX, PV, INSTR, Lds>(T, px, py, pneed);
+                mine += r.c;
+                nodes += r.nodes;
+            };
+            const bool dyn = TW > 1 && pneed >= 2;
+            int xi = wv, claim = 0;
+            if (dyn && lane == 0)
+                claim = __hip_atomic_fetch_add(&T->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            while (true) {
+                const int x = part + P * xi;
+                if (x >= d) break;
                 uint32_t bits = 0;
                 if (lane < W) {
                     bits = T->rows[x * Lds::RS + lane];
                     if constexpr (PV) bits &= gtmask(x, lane);
                 }
-                unsigned c = __popc(bits);
+                const unsigned c = __popc(bits);
                 unsigned pre = c;
 #pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    unsigned y = __shfl_up(pre, o, 64);
+                for (int o = 1; o < 32; o <<= 1) {
+                    const unsigned y = __shfl_up(pre, o, 64);
                     if (lane >= o) pre += y;
                 }
-                unsigned tot = __shfl(pre, 63, 64);
-                pre -= c;
-                unsigned pos = tail + pre;
+                const unsigned end = tail + __shfl(pre, 31, 64);
+                unsigned pos = tail + pre - c;
+                uint32_t tag;
+                if constexpr (Lds::CR) {
+                    if (end != tail) {
+                        slot = (slot + 1) & 63u;
+                        if (lane == 0) T->xs[wv][slot] = (uint16_t)x;
+                    }
+                    tag = slot << 10;
+                } else {
+                    tag = (uint32_t)x << 16;
+                }
                 while (bits) {
-                    int b = __ffs(bits) - 1;
+                    const int b = __ffs(bits) - 1;
                     bits &= bits - 1;
-                    ring[pos & (Lds::RING - 1)] = ((uint32_t)x << 16) | (uint32_t)(lane * 32 + b);
+                    ring[pos & (Lds::RING - 1)] = (RingT)(tag | (uint32_t)(lane * 32 + b));
                     ++pos;
                 }
-                tail += tot;
                 wave_fence();
-                while (tail - head >= 64) {
-                    uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                    const Acc r = do_pair<W, LMAX, PV, INSTR, Lds>(T, p, pneed);
-                    mine += r.c;
-                    nodes += r.nodes;
+                while (end - head >= 64) {
+                    take(ring[(head + lane) & (Lds::RING - 1)]);
                     head += 64;
                 }
                 wave_fence();
-            }
-            if (tail != head) {
-                if (lane < (int)(tail - head)) {
-                    uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                    const Acc r = do_pair<W, LMAX, PV, INSTR, Lds>(T, p, pneed);
-                    mine += r.c;
-                    nodes += r.nodes;
+                tail = end;
+                if (dyn) {
+                    xi = __shfl(claim, 0, 64);
+                    if (lane == 0 && part + P * xi < d)
+                        claim = __hip_atomic_fetch_add(&T->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    xi += TW;
                 }
             }
+            if (tail != head && lane < (int)(tail - head)) take(ring[(head + lane) & (Lds::RING - 1)]);
         }
     }
 
@@ -638,10 +698,11 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV>> *
 }
 
 template <int W, int LMAX, bool PV, bool INSTR>
-__global__ void __launch_bounds__(64 * TierCfg<W>::TW * TierCfg<W>::TPB)
+__global__ void __launch_bounds__((tier_threads<W, PV, LMAX>()))
 k_count(CountArgs a) {
-    using Lds = TeamLds<W, PV>;
-    constexpr int TW = TierCfg<W>::TW, TPB = TierCfg<W>::TPB;
+    using Cfg = TierCfg<W, PV, LMAX>;
+    constexpr int TW = Cfg::TW, TPB = Cfg::TPB;
+    using Lds = TeamLds<W, PV, TW>;
     extern __shared__ __align__(16) unsigned char smem[];
     const int team = threadIdx.x / (64 * TW);
     const int tlid = threadIdx.x % (64 * TW);
@@ -672,22 +733,24 @@ k_count(CountArgs a) {
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(a.total, acc);
 }
 
-template <int W, bool PV>
-constexpr size_t team_bytes() {
-    return (sizeof(TeamLds<W, PV>) + 15) & ~size_t(15);
+template <int W, bool PV, int LMAX>
+constexpr size_t block_lds() {
+    using Cfg = TierCfg<W, PV, LMAX>;
+    return ((sizeof(TeamLds<W, PV, Cfg::TW>) + 15) & ~size_t(15)) * Cfg::TPB;
 }
 
-static_assert(team_bytes<2, true>() * TierCfg<2>::TPB <= 160 * 1024, "tier 0 LDS");
-static_assert(team_bytes<4, true>() * TierCfg<4>::TPB <= 160 * 1024, "tier 1 LDS");
-static_assert(team_bytes<8, true>() * TierCfg<8>::TPB <= 160 * 1024, "tier 2 LDS");
-static_assert(team_bytes<12, true>() * TierCfg<12>::TPB <= 160 * 1024, "tier 3 LDS");
-static_assert(team_bytes<16, true>() * TierCfg<16>::TPB <= 160 * 1024, "tier 4 LDS");
-static_assert(team_bytes<24, true>() * TierCfg<24>::TPB <= 160 * 1024, "tier 5 LDS");
+template <int W>
+constexpr bool tier_fits_lds() {
+    return block_lds<W, true, 1>() <= 160 * 1024 && block_lds<W, false, 1>() <= 160 * 1024 &&
+           block_lds<W, true, 7>() <= 160 * 1024 && block_lds<W, false, 7>() <= 160 * 1024;
+}
+static_assert(tier_fits_lds<2>() && tier_fits_lds<4>() && tier_fits_lds<8>() && tier_fits_lds<12>() &&
+                  tier_fits_lds<16>() && tier_fits_lds<24>(), "a tier's block exceeds the CU's LDS");
 
 template <int W, int LMAX, bool PV, bool INSTR>
 static int launch_tier(const CountArgs &a, unsigned grid, hipStream_t s) {
-    constexpr int TW = TierCfg<W>::TW, TPB = TierCfg<W>::TPB;
-    const size_t lds = team_bytes<W, PV>() * TPB;
+    constexpr int TW = TierCfg<W, PV, LMAX>::TW, TPB = TierCfg<W, PV, LMAX>::TPB;
+    const size_t lds = block_lds<W, PV, LMAX>();
     static bool configured = false;
     if (!configured) {
         if (hipFuncSetAttribute((const void *)k_count<W, LMAX, PV, INSTR>,
@@ -722,28 +785,25 @@ static int launch_tier_rt(int tier, const CountArgs &a, unsigned grid, hipStream
         return launch_tier_rt<LM, false, false>(tier, a, grid, s);                         \
     }
 
-inline int tier_teams_per_block(int tier) {
-    switch (tier) {
-        case 0: return TierCfg<2>::TPB;
-        case 1: return TierCfg<4>::TPB;
-        case 2: return TierCfg<8>::TPB;
-        case 3: return TierCfg<12>::TPB;
-        case 4: return TierCfg<16>::TPB;
-        default: return TierCfg<24>::TPB;
-    }
+inline int tier_teams_per_block(int tier) { return tier == 0 ? TierCfg<2, false, 1>::TPB : 1; }
+
+template <int W>
+constexpr size_t tier_lds_of(bool pv, int lmax) {
+    return pv ? (lmax <= 2 ? block_lds<W, true, 1>() : block_lds<W, true, 3>())
+              : (lmax <= 2 ? block_lds<W, false, 1>() : block_lds<W, false, 3>());
 }
 
-inline size_t tier_block_lds(int tier, bool pv) {
+// LDS bytes of one block of the tier's kernel at recursion depth lmax
+inline size_t tier_block_lds(int tier, bool pv, int lmax) {
     switch (tier) {
-        case 0: return (pv ? team_bytes<2, true>() : team_bytes<2, false>()) * TierCfg<2>::TPB;
-        case 1: return (pv ? team_bytes<4, true>() : team_bytes<4, false>()) * TierCfg<4>::TPB;
-        case 2: return pv ? team_bytes<8, true>() : team_bytes<8, false>();
-        case 3: return pv ? team_bytes<12, true>() : team_bytes<12, false>();
-        case 4: return pv ? team_bytes<16, true>() : team_bytes<16, false>();
-        default: return pv ? team_bytes<24, true>() : team_bytes<24, false>();
+        case 0: return tier_lds_of<2>(pv, lmax);
+        case 1: return tier_lds_of<4>(pv, lmax);
+        case 2: return tier_lds_of<8>(pv, lmax);
+        case 3: return tier_lds_of<12>(pv, lmax);
+        case 4: return tier_lds_of<16>(pv, lmax);
+        default: return tier_lds_of<24>(pv, lmax);
     }
 }
-
 
 #define ARB_DECLARE_DEPTH(LM) \
     int launch_count_depth##LM(int tier, bool pv, bool instr, const CountArgs &a, unsigned grid, hipStream_t s);

@@ -128,6 +128,22 @@ def gnp(n: int, p: float, seed: int, name: str = "") -> Graph:
     return csr_from_pairs(n, a, b, name or f"gnp(n={n},p={p},seed={seed})")
 
 
+def sbm2(n: int, p_in: float, p_out: float, seed: int, name: str = "") -> Graph:
+    """Two-block stochastic block model: vertices [0, n/2) and [n/2, n); a pair inside a
+    block is an edge with probability p_in, a pair across the blocks with p_out.  With
+    p_out >> p_in the degrees are high while cliques stay rare (most edges are bipartite)."""
+    g = rng(seed)
+    h = n // 2
+    a0, b0 = np.triu_indices(h, 1)
+    keep = g.random(a0.size) < p_in
+    keep2 = g.random(a0.size) < p_in
+    cross = g.random((h, n - h)) < p_out
+    ca, cb = np.nonzero(cross)
+    u = np.concatenate([a0[keep], h + a0[keep2], ca]).astype(np.int64)
+    v = np.concatenate([b0[keep], h + b0[keep2], h + cb]).astype(np.int64)
+    return csr_from_pairs(n, u, v, name or f"sbm2(n={n},p_in={p_in},p_out={p_out},seed={seed})")
+
+
 def er_planted(n: int = 2000, m: int = 20000, clique: int = 30, seed: int = 1) -> Graph:
     """G(n, m) plus a clique on `clique` distinct uniformly chosen vertices (union, deduped)."""
     g = rng(seed)

@@ -102,6 +102,8 @@ COUNT_GRAPHS = [
     ("rmat14", lambda: gg.rmat(14, 200000, seed=9), range(3, 7)),
     ("rgg2d", lambda: gg.rgg(20000, 2, 20.0, 5), range(3, 9)),
     ("gnp1000", lambda: gg.gnp(1000, 0.4, 3), range(3, 5)),
+    # out-degrees spread over every tier up to ~600 with few cliques (mostly bipartite edges)
+    ("sbm1500", lambda: gg.sbm2(1500, 0.05, 0.8, 7), range(3, 7)),
 ]
 
 
