@@ -82,7 +82,12 @@ struct ListEnt {
 template <int W, bool PV, int TW_>
 struct TeamLds {
     static constexpr int D = 32 * W;             // capacity of S
-    static constexpr int RS = W + 1;             // row stride in words (odd: spreads banks)
+    // bit rows are read with Q-word loads: 128-bit loads in the two largest tiers, 32-bit
+    // loads below (measured faster there); the row stride RS is a multiple of Q with RS / Q
+    // odd, so rows start 4Q-byte aligned and the rows read by 64 lanes spread over all
+    // Q-bank groups of the LDS
+    static constexpr int Q = W >= 16 ? 4 : 1;
+    static constexpr int RS = (W / Q) % 2 == 1 ? W : W + Q;
     static constexpr int HS = pow2_at_least(D <= 128 ? 4 * D : 2 * D);
     static constexpr int HB = __builtin_ctz(HS);
     static constexpr int TW = TW_;
@@ -99,7 +104,7 @@ struct TeamLds {
     unsigned long long H[HS];
     uint32_t bm[SW];        // member bitmap over ids first .. first + SPAN - 1
     uint16_t pre[SW];       // local id of the first member in each bitmap word
-    uint32_t rows[D * RS];
+    alignas(16) uint32_t rows[D * RS];
     unsigned long long cnt[PV ? D : 1];
     union {
         RingT ring[TW][RING];       // pair phase
@@ -130,7 +135,34 @@ __device__ __forceinline__ unsigned long long lds_cas(AS3<unsigned long long> *p
 }
 
 template <int W> struct Bits { uint32_t w[W]; };
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 struct Acc { unsigned long long c, nodes; };
+
+// Words [FROM rounded down to a multiple of Q, W) of bit row z, as Q-word LDS loads; the
+// words below are left unset.
+template <int W, int FROM, class Lds>
+__device__ __forceinline__ void load_row(const AS3<Lds> *T, int z, uint32_t (&r)[W]) {
+    constexpr int Q = Lds::Q;
+    static_assert(W % Q == 0 && Lds::RS % Q == 0, "rows are whole Q-word vectors");
+    const AS3<uint32_t> *p = &T->rows[z * Lds::RS];
+#pragma unroll
+    for (int q = FROM / Q; q < W / Q; ++q) {
+        if constexpr (Q == 4) {
+            const u32x4 v = *reinterpret_cast<const AS3<u32x4> *>(p + 4 * q);
+            r[4 * q] = v.x;
+            r[4 * q + 1] = v.y;
+            r[4 * q + 2] = v.z;
+            r[4 * q + 3] = v.w;
+        } else if constexpr (Q == 2) {
+            const u32x2 v = *reinterpret_cast<const AS3<u32x2> *>(p + 2 * q);
+            r[2 * q] = v.x;
+            r[2 * q + 1] = v.y;
+        } else {
+            r[q] = p[q];
+        }
+    }
+}
 
 constexpr uint64_t kEmpty = ~0ull;
 
@@ -281,26 +313,47 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
         out.nodes += c;
     }
     if constexpr (L == 2 && !PV) {
-        // leaf level on upper rows: row z has no bits below z, so the AND starts at z's word
-// two members per step, so that the second row's LDS reads overlap the first's
+        // leaf level on upper rows: row z has no bits below z, so the AND starts at the
+        // vector holding z's word (the row's words below z's are zero)
 #pragma unroll
         for (int w = 0; w < W; ++w) {
+            constexpr int Q = Lds::Q;
+            const int v0 = (w / Q) * Q;
             uint32_t bits = J.w[w];
-            while (bits) {
-                const int z1 = w * 32 + __ffs(bits) - 1;
-                bits &= bits - 1;
-                const bool two = bits != 0;
-                const int z2 = two ? w * 32 + __ffs(bits) - 1 : z1;
-                bits &= bits - 1;
-                const AS3<uint32_t> *r1 = &T->rows[z1 * Lds::RS];
-                const AS3<uint32_t> *r2 = &T->rows[z2 * Lds::RS];
-                unsigned c1 = 0, c2 = 0;
+            if constexpr (Lds::TW >= 16) {
+                // 16-wave teams: 128 VGPRs, one member per step
+                while (bits) {
+                    const int z = w * 32 + __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    uint32_t r[W];
+                    load_row<W, 0, Lds>(T, z, r);
+                    unsigned c = 0;
 #pragma unroll
-                for (int v = w; v < W; ++v) {
-                    c1 += __popc(J.w[v] & r1[v]);
-                    c2 += __popc(J.w[v] & r2[v]);
+                    for (int v = 0; v < W; ++v)
+                        if (v >= v0) c += __popc(J.w[v] & r[v]);
+                    out.c += c;
                 }
-                out.c += c1 + (two ? c2 : 0u);
+            } else {
+                while (bits) {
+                    // two members per step, so that the second row's loads overlap the first's
+                    const int z1 = w * 32 + __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    const bool two = bits != 0;
+                    const int z2 = two ? w * 32 + __ffs(bits) - 1 : z1;
+                    bits &= bits - 1;
+                    uint32_t r1[W], r2[W];
+                    load_row<W, 0, Lds>(T, z1, r1);
+                    load_row<W, 0, Lds>(T, z2, r2);
+                    unsigned c1 = 0, c2 = 0;
+#pragma unroll
+                    for (int v = 0; v < W; ++v) {
+                        if (v >= v0) {
+                            c1 += __popc(J.w[v] & r1[v]);
+                            c2 += __popc(J.w[v] & r2[v]);
+                        }
+                    }
+                    out.c += c1 + (two ? c2 : 0u);
+                }
             }
         }
         return out;
@@ -311,7 +364,8 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
     while (true) {
         int z = pop_lowest<W>(R);
         if (z < 0) break;
-        const AS3<uint32_t> *rz = &T->rows[z * Lds::RS];
+        uint32_t rz[W];
+        load_row<W, 0, Lds>(T, z, rz);
         if constexpr (L == 2) {
             unsigned a = 0, c = 0;
 #pragma unroll
@@ -360,8 +414,9 @@ static_assert(ARB_MAX_K - 3 <= 7, "dfs_dispatch covers L up to ARB_MAX_K - 3");
 // extend it with `need` more vertices from S (need >= 1); .nodes as in dfs.
 template <int W, int LMAX, bool PV, bool INSTR, class Lds>
 __device__ __forceinline__ Acc do_pair(AS3<Lds> *T, int x, int y, int need) {
-    const AS3<uint32_t> *rx = &T->rows[x * Lds::RS];
-    const AS3<uint32_t> *ry = &T->rows[y * Lds::RS];
+    uint32_t rx[W], ry[W];
+    load_row<W, 0, Lds>(T, x, rx);
+    load_row<W, 0, Lds>(T, y, ry);
     Acc out{0ull, INSTR ? 1ull : 0ull};
     if (need == 1 || LMAX < 2) {
         if constexpr (PV) {
