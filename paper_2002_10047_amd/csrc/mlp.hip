@@ -93,6 +93,108 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const uint16_t *wb, const float
     }
 }
 
+// Inference on the matrix cores: each wave takes 16 rows at a time and computes the hidden
+// layers transposed, H'^T = W H^T, with v_mfma_f32_16x16x16_bf16 (bf16 inputs, fp32
+// accumulation).  The weights are bf16 already; each fp32 activation enters as the sum of
+// two bf16 terms (hi = rne(h), lo = rne(h - hi)), so the products keep about 16 bits of
+// the activation and the result agrees with the fp32 kernel to ~1e-5 relative.
+// Operand layout of the 16x16x16 instruction (lane l, element e in 0..3):
+//   A[i][k]: i = l % 16, k = 4 (l / 16) + e;  B[k][j]: k = 4 (l / 16) + e, j = l % 16;
+//   D[i][j]: i = 4 (l / 16) + e, j = l % 16.
+// With A = a 16x16 block of W (output unit x input unit) and B = a block of H^T (input
+// unit x row), lane l holds the row r = l % 16 in both B and D, and D's 16x16 block nb of
+// H'^T is exactly the B operand of block kb = nb for the next layer.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(const f32x4 h, bf16x4 &hi, bf16x4 &lo) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint16_t a = f32_to_bf16(h[e]);
+        hi[e] = (short)a;
+        lo[e] = (short)f32_to_bf16(h[e] - bf16_to_f32(a));
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_fwd_mfma(const uint16_t *wb, const float *x, int64_t rows, float *y) {
+    __shared__ float W[NP];
+    load_weights(wb, W);
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    // A operands of layers 2 and 3: W[nb*16 + r16][kb*16 + 4q .. +3]
+    bf16x4 A2[4][4], A3[4][4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int o = (nb * 16 + r16) * H + kb * 16 + 4 * q + e;
+                A2[nb][kb][e] = (short)wb[oW2 + o];
+                A3[nb][kb][e] = (short)wb[oW3 + o];
+            }
+    const int64_t tiles = (rows + 15) / 16;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t t = wave; t < tiles; t += nwaves) {
+        const int64_t r = t * 16 + r16;
+        const bool live = r < rows;
+        const float x0 = live ? x[3 * r] : 0.f, x1 = live ? x[3 * r + 1] : 0.f, x2 = live ? x[3 * r + 2] : 0.f;
+        // layer 1 (VALU) straight into B layout: units kb*16 + 4q + e of row r
+        bf16x4 Bhi[4], Blo[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            f32x4 h;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = kb * 16 + 4 * q + e;
+                float z = W[oB1 + j];
+                z = fmaf(W[oW1 + 3 * j + 0], x0, z);
+                z = fmaf(W[oW1 + 3 * j + 1], x1, z);
+                z = fmaf(W[oW1 + 3 * j + 2], x2, z);
+                h[e] = fmaxf(z, 0.f);
+            }
+            split_bf16(h, Bhi[kb], Blo[kb]);
+        }
+        // layers 2 and 3 on the matrix cores
+#pragma unroll
+        for (int layer = 0; layer < 2; ++layer) {
+            const int ob = layer == 0 ? oB2 : oB3;
+            f32x4 D[4];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) D[nb][e] = W[ob + nb * 16 + 4 * q + e];
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    const bf16x4 a = layer == 0 ? A2[nb][kb] : A3[nb][kb];
+                    D[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, Bhi[kb], D[nb], 0, 0, 0);
+                    D[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, Blo[kb], D[nb], 0, 0, 0);
+                }
+            }
+            if (layer == 0) {
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) {
+                    f32x4 h;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) h[e] = fmaxf(D[nb][e], 0.f);
+                    split_bf16(h, Bhi[nb], Blo[nb]);
+                }
+            } else {
+                // layer 4: this lane's 16 units of row r, then the four lanes of the row
+                float out = 0.f;
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) out = fmaf(W[oW4 + nb * 16 + 4 * q + e], fmaxf(D[nb][e], 0.f), out);
+                out += __shfl_xor(out, 16, 64);
+                out += __shfl_xor(out, 32, 64);
+                if (q == 0 && live) y[r] = out + W[oB4];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ backward
 
 // Per row: deltas of the three hidden layers (pre-activation gradients) from dy.
@@ -246,7 +348,7 @@ __global__ void k_to_bf16(const float *w, uint16_t *wb, int64_t n) {
 
 int learned_cost(const arb_ocsr *dg, const uint16_t *w, const float *feat, float *cost, hipStream_t s) {
     if (dg->n == 0) return ARB_OK;
-    k_mlp_fwd<<<grid_for(dg->n, 256, 4096), 256, 0, s>>>(w, feat, dg->n, cost, nullptr);
+    k_mlp_fwd_mfma<<<grid_for((dg->n + 15) / 16 * 64, 256, 2048), 256, 0, s>>>(w, feat, dg->n, cost);
     ARB_CHECK_LAUNCH();
     return ARB_OK;
 }
@@ -277,7 +379,11 @@ extern "C" int arb_mlp_forward(const uint16_t *w_bf16, const float *x, int64_t r
                                void *stream) {
     if (!w_bf16 || (rows > 0 && (!x || !y)) || rows < 0) { set_error(ARB_EINVAL); return ARB_EINVAL; }
     if (rows > 0) {
-        k_mlp_fwd<<<grid_for(rows, 256, 4096), 256, 0, as_stream(stream)>>>(w_bf16, x, rows, y, act);
+        if (act)
+            k_mlp_fwd<<<grid_for(rows, 256, 4096), 256, 0, as_stream(stream)>>>(w_bf16, x, rows, y, act);
+        else
+            k_mlp_fwd_mfma<<<grid_for((rows + 15) / 16 * 64, 256, 2048), 256, 0, as_stream(stream)>>>(w_bf16, x, rows,
+                                                                                                     y);
         if (hipGetLastError() != hipSuccess) { set_error(ARB_EHIP); return ARB_EHIP; }
     }
     set_error(ARB_OK);

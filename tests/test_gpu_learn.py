@@ -101,6 +101,11 @@ def test_mlp_forward_backward_against_fp64(arb):
     y_ref, cache = omlp.forward(pw, X.astype(np.float64))
     y = y.cpu().numpy()
     assert np.max(np.abs(y - y_ref)) <= 1e-4 * max(1.0, np.max(np.abs(y_ref)))
+    # inference without activations runs on the matrix cores (activations as bf16 hi + lo)
+    for rows in (5000, 16, 1, 33):
+        yi = arb.arb_mlp_forward(wb, Xd[:rows].contiguous()).cpu().numpy()
+        assert yi.shape == (rows,)
+        assert np.max(np.abs(yi - y_ref[:rows])) <= 1e-4 * max(1.0, np.max(np.abs(y_ref))), rows
     act = act.cpu().numpy().reshape(-1, 192)
     assert np.allclose(act[:, :64], cache[1], atol=1e-4 * max(1.0, np.abs(cache[1]).max()))
     g = arb.arb_mlp_backward(wb, Xd, torch.from_numpy(act.ravel().copy()).cuda(), torch.from_numpy(dy).cuda())
