@@ -12,6 +12,8 @@ Functions follow the paper (Shi, Dhulipala, Shun, arXiv 2002.10047):
   brute           the definition itself, every k-subset tested
   degeneracy      exact degeneracy, for the out-degree bound of Sec. 3.1
   local_cliques   c_j(v), the j-cliques of G[N+(v)] (the per-root work of Alg. 1)
+  local_cliques_roots  the same for listed roots (sampled checks at full size)
+  vertex_cliques  k-cliques containing listed vertices, from each one's neighbourhood
   features        the per-root scheduling features (d+, sum of d+ over N+, round)
 """
 from __future__ import annotations
@@ -60,6 +62,10 @@ def _load():
     lib.orc_degeneracy.restype = i64
     lib.orc_local_cliques.argtypes = [i64, P, P, i32, P]
     lib.orc_local_cliques.restype = None
+    lib.orc_local_cliques_roots.argtypes = [i64, P, P, i32, P, i64, i32, P]
+    lib.orc_local_cliques_roots.restype = None
+    lib.orc_vertex_cliques.argtypes = [i64, P, P, i32, P, i64, i32, P]
+    lib.orc_vertex_cliques.restype = None
     _lib = lib
     return lib
 
@@ -142,6 +148,32 @@ def local_cliques(n: int, ooff: np.ndarray, oidx: np.ndarray, jmax: int) -> np.n
     if jmax >= 1:
         _load().orc_local_cliques(n, _ptr(ooff), _ptr(oidx), int(jmax), _ptr(out))
     return out[:n, :jmax]
+
+
+def local_cliques_roots(n: int, ooff: np.ndarray, oidx: np.ndarray, jmax: int, roots, nthreads: int = 0):
+    """uint64[len(roots), jmax]: local_cliques for the listed roots only (parallel over roots)."""
+    ooff = np.ascontiguousarray(ooff, np.int64)
+    oidx = np.ascontiguousarray(oidx, np.int32)
+    if oidx.shape[0] == 0:
+        oidx = np.zeros(1, np.int32)
+    roots = np.ascontiguousarray(roots, np.int64)
+    out = np.zeros((max(roots.shape[0], 1), max(jmax, 1)), np.uint64)
+    if jmax >= 1 and roots.shape[0]:
+        _load().orc_local_cliques_roots(n, _ptr(ooff), _ptr(oidx), int(jmax), _ptr(roots), roots.shape[0],
+                                        int(nthreads), _ptr(out))
+    return out[:roots.shape[0], :jmax]
+
+
+def vertex_cliques(g, k: int, verts, nthreads: int = 0) -> np.ndarray:
+    """uint64[len(verts)]: number of k-cliques containing each listed vertex, computed from
+    its neighbourhood alone ((k-1)-cliques of G[N(v)])."""
+    off, idx = _csr(g)
+    verts = np.ascontiguousarray(verts, np.int64)
+    out = np.zeros(max(verts.shape[0], 1), np.uint64)
+    if verts.shape[0]:
+        _load().orc_vertex_cliques(g.n, _ptr(off), _ptr(idx), int(k), _ptr(verts), verts.shape[0], int(nthreads),
+                                   _ptr(out))
+    return out[:verts.shape[0]]
 
 
 def features(n: int, ooff: np.ndarray, oidx: np.ndarray, round_rank_space: np.ndarray) -> np.ndarray:

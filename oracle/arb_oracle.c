@@ -18,6 +18,10 @@
  *   orc_degeneracy          exact degeneracy (k-core / Matula-Beck order)
  *   orc_local_cliques       c_j(v) = number of j-cliques inside G[N+(v)] of a directed
  *                           graph (the per-root subproblem of Alg. 1)
+ *   orc_local_cliques_roots the same for a list of roots (sampled checks of large graphs)
+ *   orc_vertex_cliques      the number of k-cliques containing each listed vertex of an
+ *                           undirected graph, from its own neighbourhood (arb-count-v's
+ *                           per-vertex count, Sec. 3.2, by definition)
  *
  * Arithmetic: counts are uint64 modulo 2^64 (the paper fixes no width; its largest
  * printed count is below 2^63).  A 128-bit shadow of the total reports overflow.
@@ -423,4 +427,94 @@ void orc_local_cliques(int64_t n, const int64_t *ooff, const int32_t *oidx, int 
     }
     for (int j = 0; j <= jmax; j++) free(buf[j]);
     free(buf);
+}
+
+/*
+ * orc_local_cliques for the listed roots only: out[r*jmax + j-1] = number of j-cliques in
+ * G[N+(roots[r])].  Roots are independent and run in parallel when built with OpenMP.
+ */
+void orc_local_cliques_roots(int64_t n, const int64_t *ooff, const int32_t *oidx, int jmax,
+                             const int64_t *roots, int64_t nroots, int nthreads, uint64_t *out)
+{
+    int64_t dmax = 0;
+    for (int64_t r = 0; r < nroots; r++) {
+        int64_t v = roots[r];
+        if (ooff[v + 1] - ooff[v] > dmax) dmax = ooff[v + 1] - ooff[v];
+    }
+    (void)n;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        int32_t **buf = (int32_t **)malloc(sizeof(int32_t *) * (size_t)(jmax + 1));
+        for (int j = 0; j <= jmax; j++) buf[j] = (int32_t *)malloc(sizeof(int32_t) * (dmax + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t r = 0; r < nroots; r++) {
+            int64_t v = roots[r];
+            uint64_t *cj = out + r * jmax;
+            for (int j = 0; j < jmax; j++) cj[j] = 0;
+            if (jmax >= 1)
+                dag_rec(ooff, oidx, oidx + ooff[v], ooff[v + 1] - ooff[v], 1, jmax, cj, buf);
+        }
+        for (int j = 0; j <= jmax; j++) free(buf[j]);
+        free(buf);
+    }
+}
+
+/* number of `need`-cliques inside the vertex set I (ascending ids) of the undirected
+ * graph: each clique is enumerated once, in ascending id order */
+static uint64_t nbr_rec(const int64_t *off, const int32_t *idx, const int32_t *I, int64_t sz, int need,
+                        int32_t **buf)
+{
+    if (need == 0) return 1;
+    if (need == 1) return (uint64_t)sz;
+    uint64_t total = 0;
+    int32_t *J = buf[need];
+    for (int64_t i = 0; i + need <= sz; i++) {
+        int32_t u = I[i];
+        /* members of I after u that are adjacent to u (N(u) ascending) */
+        int64_t a = i + 1, b = off[u], jz = 0;
+        while (a < sz && b < off[u + 1]) {
+            if (I[a] < idx[b]) a++;
+            else if (I[a] > idx[b]) b++;
+            else { J[jz++] = I[a]; a++; b++; }
+        }
+        total += nbr_rec(off, idx, J, jz, need - 1, buf);
+    }
+    return total;
+}
+
+/*
+ * For each listed vertex v of the undirected CSR (sorted rows): out[r] = number of
+ * k-cliques that contain v = number of (k-1)-cliques inside G[N(v)] (k >= 1).
+ */
+void orc_vertex_cliques(int64_t n, const int64_t *off, const int32_t *idx, int k, const int64_t *verts,
+                        int64_t nverts, int nthreads, uint64_t *out)
+{
+    int64_t dmax = 0;
+    for (int64_t r = 0; r < nverts; r++) {
+        int64_t v = verts[r];
+        if (off[v + 1] - off[v] > dmax) dmax = off[v + 1] - off[v];
+    }
+    (void)n;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        int32_t **buf = (int32_t **)malloc(sizeof(int32_t *) * (size_t)(k + 1));
+        for (int j = 0; j <= k; j++) buf[j] = (int32_t *)malloc(sizeof(int32_t) * (dmax + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t r = 0; r < nverts; r++) {
+            int64_t v = verts[r];
+            out[r] = k < 1 ? 0 : nbr_rec(off, idx, idx + off[v], off[v + 1] - off[v], k - 1, buf);
+        }
+        for (int j = 0; j <= k; j++) free(buf[j]);
+        free(buf);
+    }
 }

@@ -276,3 +276,36 @@ def test_features_definition(orc):
     oidx = np.array([1, 2, 2], np.int32)
     f = orc.features(3, ooff, oidx, np.array([0, 0, 1]))
     assert f.tolist() == [[2, 1, 0], [1, 0, 0], [0, 0, 1]]
+
+
+def test_local_cliques_roots_agree_with_all_roots(orc):
+    # the sampled variant (parallel over listed roots) against the all-roots routine,
+    # itself pinned above by closed forms and by summing to the brute-force-pinned total
+    g = gg.rmat(12, 40000, seed=5)
+    o = orc.orient(g, 1.0)
+    full = orc.local_cliques(g.n, o["ooff"], o["oidx"], 5)
+    roots = np.random.default_rng(3).choice(g.n, 300, replace=False)
+    roots = np.concatenate([roots, np.argsort(-np.diff(o["ooff"]))[:20]])
+    for nt in (1, 4):
+        part = orc.local_cliques_roots(g.n, o["ooff"], o["oidx"], 5, roots, nthreads=nt)
+        assert np.array_equal(part, full[roots])
+    assert orc.local_cliques_roots(g.n, o["ooff"], o["oidx"], 5, np.zeros(0, np.int64)).shape == (0, 5)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_vertex_cliques_closed_forms(orc, k):
+    # K_n: every vertex is in C(n-1, k-1) k-cliques; Turan T(12,4), part sizes 3: a vertex
+    # is in e_{k-1} of the other three parts' sizes
+    g = gg.complete(13)
+    assert orc.vertex_cliques(g, k, np.arange(13)).tolist() == [math.comb(12, k - 1)] * 13
+    t = gg.turan(12, 4)
+    e = [1, 9, 27, 27][k - 1] if k <= 4 else 0
+    assert orc.vertex_cliques(t, k, np.arange(12)).tolist() == [e] * 12
+
+
+def test_vertex_cliques_agree_with_per_vertex_count(orc):
+    for g in [gg.gnp(120, 0.3, 7), gg.config_graph("c1"), gg.rmat(11, 20000, seed=8)]:
+        verts = np.random.default_rng(1).choice(g.n, min(g.n, 150), replace=False)
+        for k in (3, 4, 5):
+            _, pv = orc.count(g, k, per_vertex=True, nthreads=4)
+            assert np.array_equal(orc.vertex_cliques(g, k, verts, nthreads=4), pv[verts]), (g.name, k)
