@@ -108,6 +108,25 @@ int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *out,
                int32_t *rank, int32_t *round, int32_t *deg_at_peel, int64_t *stats,
                void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace of arb_orient_batch for a union of G graphs. */
+size_t arb_orient_batch_workspace(int64_t n, int64_t nnz, int64_t G);
+
+/* arb_orient for a batch: g is the disjoint union of G graphs, graph i on the vertex
+ * range graph_vtx_offsets[i] .. graph_vtx_offsets[i+1]-1 (device int64[G+1], 0 = first,
+ * n = last, non-decreasing; no edge between graphs).  Each graph is peeled with its own
+ * remaining count, degree sum and threshold per round (Alg. 4 applied to every graph),
+ * so every graph gets exactly the orientation, rounds and degrees at removal that
+ * arb_orient gives it alone, shifted by its first vertex; its ranks stay inside its own
+ * range, so per-graph results of arb_count are contiguous in rank space.  max_graph_n
+ * (host) is the largest graph's vertex count and bounds the number of rounds.
+ * validate = 1 also checks the ranges and that no edge crosses graphs (ARB_EGRAPH);
+ * without it, malformed ranges give wrong results but no access outside the buffers.
+ * stats (nullable): stats[0] = rounds used, stats[1] = largest out-degree.  Other
+ * arguments and errors as arb_orient. */
+int arb_orient_batch(const arb_csr *g, const int64_t *graph_vtx_offsets, int64_t G, int64_t max_graph_n,
+                     double eps, int validate, arb_ocsr *out, int32_t *rank, int32_t *round_out,
+                     int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* Check an undirected CSR: returns ARB_OK or ARB_EGRAPH (synchronises). */
 int arb_validate(const arb_csr *g, void *ws, size_t ws_bytes, void *stream);
 
@@ -188,6 +207,18 @@ int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *pe
  * disjoint union of G graphs, this yields the per-graph totals of a batch. */
 int arb_segment_sum_u64(const uint64_t *in, const int64_t *offsets, int64_t G, uint64_t *out,
                         void *stream);
+
+/* Workspace of arb_count_batch_async. */
+size_t arb_count_batch_workspace(int64_t n, int64_t m, int k, int64_t G);
+
+/* Per-graph k-clique totals of a batch oriented by arb_orient_batch (its rank ranges are
+ * the graphs' vertex ranges): totals_dev[i] (device uint64[G]) = k-cliques of graph i,
+ * total_dev (device, nullable) = their sum, per_vertex (nullable, rank space) as in
+ * arb_count_async.  graph_vtx_offsets: device int64[G+1] as given to arb_orient_batch.
+ * Asynchronous and capture-safe in the persistent schedules; errors as arb_count_async. */
+int arb_count_batch_async(const arb_ocsr *dg, const int64_t *graph_vtx_offsets, int64_t G, int k,
+                          uint64_t *per_vertex, uint64_t *totals_dev, uint64_t *total_dev,
+                          const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /* Synchronous arb_count_async that also checks dg first; returns the total, or 0 with
  * arb_last_error() != ARB_OK on failure.  Synchronises the stream. */

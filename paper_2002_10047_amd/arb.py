@@ -66,6 +66,10 @@ P, I64, I32, SZ, DBL, FLT = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctyp
 _sigs = {
     "arb_orient_workspace": ([I64, I64], SZ),
     "arb_orient": ([P, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
+    "arb_orient_batch_workspace": ([I64, I64, I64], SZ),
+    "arb_orient_batch": ([P, P, I64, I64, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
+    "arb_count_batch_workspace": ([I64, I64, I32, I64], SZ),
+    "arb_count_batch_async": ([P, P, I64, I32, P, P, P, P, P, SZ, P], I32),
     "arb_validate": ([P, P, SZ, P], I32),
     "arb_check_oriented": ([P, P, SZ, P], I32),
     "arb_permute_u64": ([P, P, P, I64, P], I32),
@@ -176,6 +180,46 @@ def arb_orient(offsets: torch.Tensor, indices: torch.Tensor, eps: float = 1.0, v
                 stats=stats, n=n, m=nnz // 2)
 
 
+def arb_orient_batch_workspace(n: int, nnz: int, G: int) -> int:
+    return int(_lib.arb_orient_batch_workspace(n, nnz, G))
+
+
+def arb_orient_batch(offsets: torch.Tensor, indices: torch.Tensor, graph_vtx_offsets, eps: float = 1.0,
+                     validate: bool = False, stream=None, max_graph_n=None):
+    """arb_orient_batch on a disjoint union; graph_vtx_offsets: int64[G+1], host (numpy)
+    or a device tensor (then max_graph_n is required, and nothing is copied, so the call
+    can be captured).  Returns the arb_orient dict plus vo (device offsets) and G."""
+    n = offsets.numel() - 1
+    nnz = indices.numel()
+    dev = offsets.device
+    if torch.is_tensor(graph_vtx_offsets) and graph_vtx_offsets.is_cuda:
+        if max_graph_n is None:
+            raise ValueError("max_graph_n is required with device offsets")
+        vo = graph_vtx_offsets
+        G = vo.numel() - 1
+        max_n = int(max_graph_n)
+    else:
+        vo_h = np.asarray(graph_vtx_offsets, dtype=np.int64)
+        G = vo_h.shape[0] - 1
+        vo = torch.from_numpy(vo_h.copy()).to(dev)
+        max_n = int(np.diff(vo_h).max()) if G > 0 else 0
+    g = ArbCsr(n, nnz, offsets.data_ptr(), indices.data_ptr() if nnz else 0)
+    ooff = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    oidx = torch.empty(max(nnz // 2, 1), dtype=torch.int32, device=dev)
+    out = ArbOcsr(n, nnz // 2, ooff.data_ptr(), oidx.data_ptr())
+    rank = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rnd = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    dap = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    stats = torch.empty(2 + ARB_MAX_ROUNDS, dtype=torch.int64, device=dev)
+    ws = _ws(_lib.arb_orient_batch_workspace(n, nnz, max(G, 1)), dev)
+    rc = _lib.arb_orient_batch(ctypes.byref(g), _ptr(vo), G, max_n, float(eps), int(bool(validate)),
+                               ctypes.byref(out), _ptr(rank), _ptr(rnd), _ptr(dap), _ptr(stats), _ptr(ws),
+                               ws.numel(), _stream(stream))
+    _check(rc, "arb_orient_batch")
+    return dict(ooff=ooff, oidx=oidx[: nnz // 2], rank=rank[:n], round=rnd[:n], deg_at_peel=dap[:n],
+                stats=stats, n=n, m=nnz // 2, vo=vo, G=G)
+
+
 def arb_validate(offsets, indices, stream=None) -> int:
     n = offsets.numel() - 1
     g = ArbCsr(n, indices.numel(), offsets.data_ptr(), indices.data_ptr() if indices.numel() else 0)
@@ -261,6 +305,27 @@ def arb_count_async(ooff, oidx, k, total=None, per_vertex=None, work=None, opts=
                               _stream(stream))
     _check(rc, "arb_count_async")
     return total
+
+
+def arb_count_batch_workspace(n: int, m: int, k: int, G: int) -> int:
+    return int(_lib.arb_count_batch_workspace(n, m, k, G))
+
+
+def arb_count_batch_async(ooff, oidx, vo, k, totals=None, total=None, per_vertex=None, opts=None, ws=None,
+                          stream=None):
+    """Per-graph totals (device int64[G] holding uint64) of a batch from arb_orient_batch;
+    vo: its device vertex offsets; ws: a byte tensor of arb_count_batch_workspace bytes."""
+    dg = _ocsr(ooff, oidx)
+    G = vo.numel() - 1
+    if ws is None:
+        ws = _ws(_lib.arb_count_batch_workspace(dg.n, dg.m, int(k), G), ooff.device)
+    if totals is None:
+        totals = torch.empty(max(G, 1), dtype=torch.int64, device=ooff.device)
+    rc = _lib.arb_count_batch_async(ctypes.byref(dg), _ptr(vo), G, int(k), _ptr(per_vertex), _ptr(totals),
+                                    _ptr(total), ctypes.byref(opts) if opts is not None else None, _ptr(ws),
+                                    ws.numel(), _stream(stream))
+    _check(rc, "arb_count_batch_async")
+    return totals[:G]
 
 
 def arb_count(ooff, oidx, k, per_vertex: bool = False, opts=None, ws=None, stream=None):

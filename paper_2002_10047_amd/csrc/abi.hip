@@ -46,6 +46,36 @@ extern "C" int arb_segment_sum_u64(const uint64_t *in, const int64_t *offsets, i
     return ARB_OK;
 }
 
+// Batch counting: per-root counts of the union, then per-graph sums over the rank ranges
+// (contiguous per graph after arb_orient_batch).  Workspace: the count's, then the
+// per-root counts and the grand total.
+static size_t batch_extra(int64_t n) { return ((size_t)(n > 0 ? n : 1) + 1) * sizeof(uint64_t) + 256; }
+
+extern "C" size_t arb_count_batch_workspace(int64_t n, int64_t m, int k, int64_t G) {
+    (void)G;
+    return ((arb_count_workspace(n, m, k) + 255) & ~size_t(255)) + batch_extra(n);
+}
+
+extern "C" int arb_count_batch_async(const arb_ocsr *dg, const int64_t *graph_vtx_offsets, int64_t G, int k,
+                                     uint64_t *per_vertex, uint64_t *totals_dev, uint64_t *total_dev,
+                                     const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+    if (!dg || !graph_vtx_offsets || !totals_dev || !ws || G < 1 || dg->n < 0 || G > dg->n + 1) {
+        set_error(ARB_EINVAL);
+        return ARB_EINVAL;
+    }
+    const int64_t n = dg->n;
+    const size_t cws = (arb_count_workspace(n, dg->m, k) + 255) & ~size_t(255);
+    if (ws_bytes < cws + batch_extra(n)) {
+        set_error(ARB_EWORKSPACE);
+        return ARB_EWORKSPACE;
+    }
+    uint64_t *per_root = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + cws);
+    uint64_t *total = total_dev ? total_dev : per_root + (n > 0 ? n : 1);
+    int rc = arb_count_async(dg, k, total, per_vertex, per_root, nullptr, opts, ws, cws, stream);
+    if (rc) return rc;
+    return arb_segment_sum_u64(per_root, graph_vtx_offsets, G, totals_dev, stream);
+}
+
 extern "C" int arb_permute_u64(const int32_t *rank, const uint64_t *in, uint64_t *out, int64_t n, void *stream) {
     if (n < 0 || (n > 0 && (!rank || !in || !out)) || in == out) {
         set_error(ARB_EINVAL);

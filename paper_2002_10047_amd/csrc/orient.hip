@@ -20,7 +20,7 @@ constexpr int kDegBits = 26;   // degree at removal packed below the round in th
 
 enum : int32_t {
     kErrOffsets = 1, kErrRange = 2, kErrSelf = 4, kErrOrder = 8, kErrAsym = 16,
-    kErrDegree = 32, kErrRowLong = 64, kErrLeft = 128
+    kErrDegree = 32, kErrRowLong = 64, kErrLeft = 128, kErrBatch = 256
 };
 
 // ------------------------------------------------------------------ validation
@@ -162,6 +162,112 @@ __global__ void k_copy_rounds(int64_t n, const int32_t *src, int32_t *dst) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x)
         dst[v] = src[v];
+}
+
+// ------------------------------------------------------------------ batches
+// A disjoint union of G graphs, graph g on the vertex range vo[g] .. vo[g+1]-1, is peeled
+// with each graph's own n_r, S_r and T_r, so that every graph is oriented exactly as on
+// its own; ranks stay inside each graph's range.
+
+// gid was zero-filled first; ranges are clamped to [0, n), so malformed offsets (caught
+// by the range check when validating) cannot write outside gid or leave an id >= G
+__global__ void k_gid_fill(int64_t n, int64_t G, const int64_t *vo, int32_t *gid) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t g = wave; g < G; g += nwaves) {
+        const int64_t lo = vo[g] < 0 ? 0 : vo[g], hi = vo[g + 1] > n ? n : vo[g + 1];
+        for (int64_t v = lo + lane; v < hi; v += 64) gid[v] = (int32_t)g;
+    }
+}
+
+// vertex ranges: vo[0] = 0, vo[G] = n, non-decreasing
+__global__ void k_check_ranges(int64_t n, int64_t G, const int64_t *vo, int32_t *err) {
+    int32_t bad = 0;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x)
+        if (vo[g + 1] < vo[g]) bad = kErrBatch;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (vo[0] != 0 || vo[G] != n)) bad = kErrBatch;
+    if (bad) atomicOr(err, bad);
+}
+
+// every edge stays inside its graph
+__global__ void k_check_batch_edges(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *gid,
+                                    int32_t *err) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int32_t bad = 0;
+    for (int64_t v = wave; v < n; v += nwaves)
+        for (int64_t p = off[v] + lane; p < off[v + 1]; p += 64)
+            if (gid[idx[p]] != gid[v]) bad = kErrBatch;
+    if (bad) atomicOr(err, bad);
+}
+
+// rs[2g], rs[2g+1] = number present in graph g and the sum of their degrees (rs zeroed
+// before each round).  A wave whose 64 vertices share one graph adds its sums once.
+__global__ void k_bpeel_reduce(int64_t n, const int32_t *deg, const int32_t *rnd, const int32_t *gid, int64_t *rs) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+        const int64_t v = base + lane;
+        const bool in = v < n;
+        const bool present = in && rnd[v] == kPresent;
+        int64_t c = present ? 1 : 0, sd = present ? deg[v] : 0;
+        const int32_t g = in ? gid[v] : -1;
+        const int32_t g0 = __shfl(g, 0, 64);
+        if (__all(!in || g == g0)) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                c += __shfl_xor(c, o, 64);
+                sd += __shfl_xor(sd, o, 64);
+            }
+            if (lane == 0 && c) {
+                atomicAdd((unsigned long long *)&rs[2 * g0], (unsigned long long)c);
+                atomicAdd((unsigned long long *)&rs[2 * g0 + 1], (unsigned long long)sd);
+            }
+        } else if (present) {
+            atomicAdd((unsigned long long *)&rs[2 * g], 1ull);
+            atomicAdd((unsigned long long *)&rs[2 * g + 1], (unsigned long long)sd);
+        }
+    }
+}
+
+// thr[g] = T_r of graph g (-1 when it is empty); any[r] = the largest of them, so that
+// rounds with nothing left skip their work; stats[0] = rounds that peeled.
+__global__ void k_bpeel_threshold(int64_t G, int r, double eps, const int64_t *rs, int64_t *thr, int64_t *any,
+                                  int64_t *stats) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = rs[2 * g], S = rs[2 * g + 1];
+        if (c == 0) {
+            thr[g] = -1;
+            continue;
+        }
+        double num = (2.0 + eps) * (double)S;
+        double t = num / (double)c;
+        const int64_t T = (int64_t)floor(t);
+        thr[g] = T;
+        atomicMax((long long *)&any[r], (long long)T);
+        if (stats) atomicMax((long long *)&stats[0], (long long)(r + 1));
+    }
+}
+
+__global__ void k_bpeel_mark(int64_t n, const int32_t *deg, int32_t *rnd, int32_t *dap, const int32_t *gid, int r,
+                             const int64_t *thr, const int64_t *any) {
+    if (any[r] < 0) return;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (rnd[v] == kPresent && (int64_t)deg[v] <= thr[gid[v]]) {
+            rnd[v] = r;
+            dap[v] = deg[v];
+        }
+    }
+}
+
+// second sort key: the graph of the vertex at each position
+__global__ void k_gid_keys(int64_t n, const int32_t *vals, const int32_t *gid, uint32_t *keys) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        keys[p] = (uint32_t)gid[vals[p]];
 }
 
 // ------------------------------------------------------------------ rank
@@ -323,11 +429,21 @@ struct OrientWs {
     int32_t *vals, *vals_alt;
     int64_t *rs, *thr, *outdeg;
     void *scan_ws, *radix_ws;
+    int32_t *gid;            // batches: graph of each vertex
+    int64_t *rs_g, *thr_g;   // batches: per-graph round sums and thresholds
 };
 
-static size_t carve_orient(Carver &c, int64_t n, int64_t nnz, OrientWs *w) {
+static size_t carve_orient(Carver &c, int64_t n, int64_t nnz, OrientWs *w, int64_t G = 0) {
     (void)nnz;
     int64_t nn = n > 0 ? n : 1;
+    if (G > 0) {
+        w->gid = c.take<int32_t>(nn);
+        w->rs_g = c.take<int64_t>(2 * G);
+        w->thr_g = c.take<int64_t>(G);
+    } else {
+        w->gid = nullptr;
+        w->rs_g = w->thr_g = nullptr;
+    }
     w->deg = c.take<int32_t>(nn);
     w->rnd = c.take<int32_t>(nn);
     w->dap = c.take<int32_t>(nn);
@@ -382,80 +498,144 @@ extern "C" int arb_validate(const arb_csr *g, void *ws, size_t ws_bytes, void *s
     return rc;
 }
 
-extern "C" int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *out, int32_t *rank,
-                          int32_t *round_out, int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes,
-                          void *stream) {
-    hipStream_t s = as_stream(stream);
-    auto fail = [](int rc) { set_error(rc); return rc; };
-    if (!g || !out || !rank || !ws) return fail(ARB_EINVAL);
-    if (!(eps >= 0.0 && eps <= 64.0)) return fail(ARB_EINVAL);
+struct BatchDesc {
+    const int64_t *vo;       // device, G + 1 vertex offsets
+    int64_t G;
+    int64_t max_n;           // largest graph (bounds the number of rounds)
+};
+
+static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out, int32_t *rank,
+                       int32_t *round_out, int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes,
+                       hipStream_t s, const BatchDesc *b) {
+    if (!g || !out || !rank || !ws) return ARB_EINVAL;
+    if (!(eps >= 0.0 && eps <= 64.0)) return ARB_EINVAL;
     const int64_t n = g->n, nnz = g->nnz;
-    if (n < 0 || nnz < 0 || (nnz & 1)) return fail(ARB_EINVAL);
-    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) return fail(ARB_ELIMIT);
+    if (n < 0 || nnz < 0 || (nnz & 1)) return ARB_EINVAL;
+    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) return ARB_ELIMIT;
     if (!g->offsets || (nnz > 0 && !g->indices) || !out->offsets || (nnz > 0 && !out->indices))
-        return fail(ARB_EINVAL);
-    if (out->n != n || out->m != nnz / 2) return fail(ARB_EINVAL);
-    if (ws_bytes < arb_orient_workspace(n, nnz)) return fail(ARB_EWORKSPACE);
+        return ARB_EINVAL;
+    if (out->n != n || out->m != nnz / 2) return ARB_EINVAL;
+    const int64_t G = b ? b->G : 0;
+    if (b && (G < 1 || G > n + 1 || !b->vo || b->max_n < 0 || b->max_n > n)) return ARB_EINVAL;
+    const size_t need = b ? arb_orient_batch_workspace(n, nnz, G) : arb_orient_workspace(n, nnz);
+    if (ws_bytes < need) return ARB_EWORKSPACE;
 
     Carver cv(ws);
     OrientWs w;
-    carve_orient(cv, n, nnz, &w);
+    carve_orient(cv, n, nnz, &w, G);
     int rc;
     if (validate) {
         rc = validate_impl(g, w.err, s);
-        if (rc) return fail(rc);
+        if (rc) return rc;
     }
-    if ((rc = fill_i32(w.err, 0, 1, s))) return fail(rc);
-    if ((rc = fill_i64(w.rs, 0, 2 * 128, s))) return fail(rc);
-    if ((rc = fill_i64(w.thr, -1, 128, s))) return fail(rc);
-    if (stats && (rc = fill_i64(stats, 0, 2 + ARB_MAX_ROUNDS, s))) return fail(rc);
+    if ((rc = fill_i32(w.err, 0, 1, s))) return rc;
+    if ((rc = fill_i64(w.rs, 0, 2 * 128, s))) return rc;
+    if ((rc = fill_i64(w.thr, -1, 128, s))) return rc;
+    if (stats && (rc = fill_i64(stats, 0, 2 + ARB_MAX_ROUNDS, s))) return rc;
     int32_t *dap = dap_out ? dap_out : w.dap;
     int32_t *rnd = w.rnd;
 
     const unsigned gb = grid_for(n, 256, 2048);
-    k_orient_init<<<gb, 256, 0, s>>>(n, g->offsets, w.deg, rnd, w.err);
-    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
-    const int R = max_rounds(n, eps);
-    if (R > 120) return fail(ARB_ELIMIT);
     const unsigned gw = grid_for(n, 256, 4096);
+    if (b) {
+        k_check_ranges<<<grid_for(G, 256, 1024), 256, 0, s>>>(n, G, b->vo, w.err);
+        if ((rc = fill_i32(w.gid, 0, n > 0 ? n : 1, s))) return rc;
+        k_gid_fill<<<grid_for(G * 64, 256, 4096), 256, 0, s>>>(n, G, b->vo, w.gid);
+        if (hipGetLastError() != hipSuccess) return ARB_EHIP;
+        if (validate) {
+            if (n > 0)
+                k_check_batch_edges<<<grid_for(n * 64, 256, 8192), 256, 0, s>>>(n, g->offsets, g->indices, w.gid,
+                                                                               w.err);
+            int32_t h = 0;
+            if (hipMemcpyAsync(&h, w.err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return ARB_EHIP;
+            if (h) return ARB_EGRAPH;
+        }
+    }
+    k_orient_init<<<gb, 256, 0, s>>>(n, g->offsets, w.deg, rnd, w.err);
+    if (hipGetLastError() != hipSuccess) return ARB_EHIP;
+    const int R = max_rounds(b ? b->max_n : n, eps);
+    if (R > 120) return ARB_ELIMIT;
     for (int r = 0; r < R; ++r) {
-        k_peel_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, r, w.rs);
-        k_peel_threshold<<<1, 64, 0, s>>>(r, eps, w.rs, w.thr, stats);
-        k_peel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, w.thr);
+        if (b) {
+            if ((rc = fill_i64(w.rs_g, 0, 2 * G, s))) return rc;
+            k_bpeel_reduce<<<gw, 256, 0, s>>>(n, w.deg, rnd, w.gid, w.rs_g);
+            k_bpeel_threshold<<<grid_for(G, 256, 1024), 256, 0, s>>>(G, r, eps, w.rs_g, w.thr_g, w.thr, stats);
+            k_bpeel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, w.gid, r, w.thr_g, w.thr);
+        } else {
+            k_peel_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, r, w.rs);
+            k_peel_threshold<<<1, 64, 0, s>>>(r, eps, w.rs, w.thr, stats);
+            k_peel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, w.thr);
+        }
         k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, w.thr);
     }
     k_count_left<<<gb, 256, 0, s>>>(n, rnd, w.err);
-    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
-    // rank: stable sort of ids by (round, degree at removal)
+    if (hipGetLastError() != hipSuccess) return ARB_EHIP;
+    // rank: stable sort of ids by (round, degree at removal); in a batch then stably by
+    // graph, which keeps every graph's ranks inside its own vertex range
     k_rank_keys<<<gb, 256, 0, s>>>(n, rnd, dap, w.keys, w.vals);
-    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     int round_bits = 1;
     while ((1 << round_bits) <= R) ++round_bits;
-    if (kDegBits + round_bits > 32) return fail(ARB_ELIMIT);
+    if (kDegBits + round_bits > 32) return ARB_ELIMIT;
     if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, kDegBits + round_bits, w.radix_ws, s)))
-        return fail(rc);
+        return rc;
+    if (b && G > 1) {
+        k_gid_keys<<<gb, 256, 0, s>>>(n, w.vals, w.gid, w.keys);
+        if (hipGetLastError() != hipSuccess) return ARB_EHIP;
+        int gbits = 1;
+        while ((int64_t(1) << gbits) < G) ++gbits;
+        if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, gbits, w.radix_ws, s))) return rc;
+    }
     k_rank_scatter<<<gb, 256, 0, s>>>(n, w.vals, rank);
     // directing
     const unsigned gv = grid_for(n * 64, 256, 8192);
     k_dir_count<<<gv, 256, 0, s>>>(n, g->offsets, g->indices, rank, w.outdeg);
-    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
-    if ((rc = exclusive_scan_i64(w.outdeg, out->offsets, n, w.scan_ws, s))) return fail(rc);
+    if (hipGetLastError() != hipSuccess) return ARB_EHIP;
+    if ((rc = exclusive_scan_i64(w.outdeg, out->offsets, n, w.scan_ws, s))) return rc;
     k_dir_fill<<<gv, 256, 0, s>>>(n, g->offsets, g->indices, rank, out->offsets, out->indices);
     k_row_sort_small<<<gv, 256, 0, s>>>(n, out->offsets, out->indices, stats);
     k_row_sort_mid<<<grid_for(n, 1, 8192), 256, 0, s>>>(n, out->offsets, out->indices);
     k_row_sort_big<<<grid_for(n, 64, 256), 256, ARB_MAX_ROW_SORT * sizeof(int32_t), s>>>(
         n, out->offsets, out->indices, w.err);
-    if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+    if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     if (round_out) {
         k_copy_rounds<<<gb, 256, 0, s>>>(n, rnd, round_out);
-        if (hipGetLastError() != hipSuccess) return fail(ARB_EHIP);
+        if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     }
     if (validate) {
         int32_t h = 0;
         if (hipMemcpyAsync(&h, w.err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
-            return fail(ARB_EHIP);
-        if (h) return fail(ARB_ELIMIT);
+            return ARB_EHIP;
+        if (h & kErrBatch) return ARB_EGRAPH;
+        if (h) return ARB_ELIMIT;
     }
-    return fail(ARB_OK);
+    return ARB_OK;
+}
+
+extern "C" size_t arb_orient_batch_workspace(int64_t n, int64_t nnz, int64_t G) {
+    Carver c(nullptr);
+    OrientWs w;
+    return carve_orient(c, n, nnz, &w, G > 0 ? G : 1) + 256;
+}
+
+extern "C" int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *out, int32_t *rank,
+                          int32_t *round_out, int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes,
+                          void *stream) {
+    const int rc = orient_impl(g, eps, validate, out, rank, round_out, dap_out, stats, ws, ws_bytes,
+                               as_stream(stream), nullptr);
+    set_error(rc);
+    return rc;
+}
+
+extern "C" int arb_orient_batch(const arb_csr *g, const int64_t *graph_vtx_offsets, int64_t G, int64_t max_graph_n,
+                                double eps, int validate, arb_ocsr *out, int32_t *rank, int32_t *round_out,
+                                int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes, void *stream) {
+    const BatchDesc b{graph_vtx_offsets, G, max_graph_n};
+    const int rc = orient_impl(g, eps, validate, out, rank, round_out, dap_out, stats, ws, ws_bytes,
+                               as_stream(stream), &b);
+    set_error(rc);
+    return rc;
 }

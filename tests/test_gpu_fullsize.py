@@ -1,0 +1,165 @@
+"""Parity at the full size of the R-MAT scale-20 workload (2^20 vertices, 15.7M edges) in
+the launch configuration bench.py times: learned schedule, tuned options from the cache,
+concurrent tier kernels.  The oracle cannot count k = 4, 5 on the whole graph in test time,
+so it checks sampled outputs one by one -- per-root counts (the (k-1)-cliques of
+G[N+(v)] on the GPU's own orientation, heaviest roots included) and per-vertex counts
+(from each sampled vertex's neighbourhood) -- plus properties that hold at any size:
+per-root counts sum to the total, per-vertex counts to k times the total.  The k = 3
+total is checked whole."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2002_10047_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def arb():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2002_10047_amd.arb as arb
+    return arb
+
+
+@pytest.fixture(scope="module")
+def c2(arb):
+    say("generating R-MAT scale 20")
+    g = gg.config_graph("c2")
+    off, idx = arb.to_device_csr(g)
+    o = arb.arb_orient(off, idx, eps=1.0)
+    feat = arb.arb_features(o["ooff"], o["oidx"], o["round"], o["rank"])
+    host = dict(ooff=o["ooff"].cpu().numpy(), oidx=o["oidx"].cpu().numpy(), rank=o["rank"].cpu().numpy())
+    return g, o, feat, host
+
+
+def bench_opts(arb, o, feat, k, ws):
+    from paper_2002_10047_amd import learn, tuning
+    w = learn.load_weights(k)
+    assert w is not None, f"no trained cost model for k={k}"
+    op, _ = tuning.tuned_opts(o["ooff"], o["oidx"], k, "learned", mlp_weights=w, features=feat, ws=ws)
+    op._keep = (w, feat)
+    return op
+
+
+def sample_roots(d, k, rng):
+    live = np.nonzero(d >= k - 1)[0]
+    heavy = np.argsort(-d)[: (20 if k >= 5 else 100)]
+    bounds = [0, 64, 128, 256, 384, 512, 768]
+    per_tier = []
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        t = live[(d[live] > lo) & (d[live] <= hi)]
+        if t.size:
+            per_tier.append(rng.choice(t, min(t.size, 200 if hi <= 256 else 40), replace=False))
+    return np.unique(np.concatenate([heavy, *per_tier, rng.choice(live, 1000, replace=False)]))
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_full_c2_per_root_sampled(arb, orc, c2, k):
+    g, o, feat, host = c2
+    n = g.n
+    ws = arb.CountWorkspace(o["ooff"], o["oidx"], k)
+    per_root = torch.empty(n, dtype=torch.int64, device="cuda")
+    total = torch.empty(1, dtype=torch.int64, device="cuda")
+    arb.arb_count_async(o["ooff"], o["oidx"], k, total=total, per_root=per_root, opts=bench_opts(arb, o, feat, k, ws),
+                        ws=ws)
+    torch.cuda.synchronize()
+    pr = arb.u64_numpy(per_root)
+    t = int(arb.u64_numpy(total)[0])
+    assert int(pr.sum(dtype=np.uint64)) == t
+    d = np.diff(host["ooff"])
+    roots = sample_roots(d, k, np.random.default_rng(100 + k))
+    say("k", k, "total", t, "checking", roots.size, "roots; max d+ among them", int(d[roots].max()))
+    ref = orc.local_cliques_roots(n, host["ooff"], host["oidx"], k - 1, roots, nthreads=16)
+    assert np.array_equal(pr[roots], ref[:, k - 2])
+    if k == 3:
+        assert t == orc.count(g, 3, nthreads=16)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_full_c2_per_vertex_sampled(arb, orc, c2, k):
+    g, o, feat, host = c2
+    deg = np.diff(g.offsets)
+    cap = 3000 if k <= 4 else 500
+    ok = np.nonzero(deg <= cap)[0]
+    rng = np.random.default_rng(200 + k)
+    verts = np.unique(np.concatenate([rng.choice(ok, 300, replace=False), ok[np.argsort(-deg[ok])[:20]]]))
+    ws = arb.CountWorkspace(o["ooff"], o["oidx"], k)
+    op = bench_opts(arb, o, feat, k, ws)
+    t, pv_rank = arb.arb_count(o["ooff"], o["oidx"], k, per_vertex=True, opts=op, ws=ws)
+    assert int(pv_rank.sum(dtype=np.uint64)) == (k * t) % (1 << 64)
+    pv = pv_rank[host["rank"]]                      # back to the generator's vertex ids
+    say("k", k, "per-vertex: checking", verts.size, "vertices of degree <=", cap)
+    ref = orc.vertex_cliques(g, k, verts, nthreads=16)
+    assert np.array_equal(pv[verts], ref)
+
+
+def golden_totals(name):
+    import json
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_totals.json")
+    with open(p) as f:
+        return json.load(f)[name]
+
+
+def test_full_c2_totals_golden(arb, c2):
+    # k = 3, 4 totals of the whole graph against the oracle's (tests/golden/make_fullsize.py)
+    g, o, feat, host = c2
+    ref = golden_totals("c2")
+    assert (ref["n"], ref["m"]) == (g.n, g.m)
+    for k in (3, 4):
+        ws = arb.CountWorkspace(o["ooff"], o["oidx"], k)
+        assert arb.arb_count(o["ooff"], o["oidx"], k, opts=bench_opts(arb, o, feat, k, ws), ws=ws) == \
+            ref["totals"][str(k)]
+
+
+@pytest.fixture(scope="module")
+def c3(arb):
+    say("generating Chung-Lu n=2^22 with 1000 planted communities")
+    g = gg.config_graph("c3")
+    off, idx = arb.to_device_csr(g)
+    o = arb.arb_orient(off, idx, eps=1.0)
+    host = dict(ooff=o["ooff"].cpu().numpy(), oidx=o["oidx"].cpu().numpy(), rank=o["rank"].cpu().numpy())
+    return g, o, host
+
+
+@pytest.mark.parametrize("k", [6, 7, 8])
+def test_full_c3_totals_and_samples(arb, orc, c3, k):
+    """Chung-Lu 2^22 vertices (exponent 2.1, 2^26 pairs, weights capped at 4000) with 1000
+    planted communities of 40-80 vertices at edge probability 1/2: the deep-recursion
+    workload.  Totals against the oracle's; per-root counts of the heaviest and of random
+    roots, and per-vertex counts of community-sized neighbourhoods, one by one."""
+    g, o, host = c3
+    ref = golden_totals("c3")
+    assert (ref["n"], ref["m"]) == (g.n, g.m)
+    n = g.n
+    ws = arb.CountWorkspace(o["ooff"], o["oidx"], k)
+    per_root = torch.empty(n, dtype=torch.int64, device="cuda")
+    total = torch.empty(1, dtype=torch.int64, device="cuda")
+    arb.arb_count_async(o["ooff"], o["oidx"], k, total=total, per_root=per_root, ws=ws)
+    torch.cuda.synchronize()
+    t = int(arb.u64_numpy(total)[0])
+    assert t == ref["totals"][str(k)]
+    pr = arb.u64_numpy(per_root)
+    assert int(pr.sum(dtype=np.uint64)) == t
+    d = np.diff(host["ooff"])
+    roots = sample_roots(d, k, np.random.default_rng(300 + k))
+    roots = np.unique(np.concatenate([roots, np.nonzero(pr)[0][:2000]]))    # roots that own cliques
+    say("k", k, "total", t, "checking", roots.size, "roots")
+    lc = orc.local_cliques_roots(n, host["ooff"], host["oidx"], k - 1, roots, nthreads=16)
+    assert np.array_equal(pr[roots], lc[:, k - 2])
+    tp, pv_rank = arb.arb_count(o["ooff"], o["oidx"], k, per_vertex=True, ws=ws)
+    assert tp == t and int(pv_rank.sum(dtype=np.uint64)) == (k * t) % (1 << 64)
+    pv = pv_rank[host["rank"]]
+    deg = np.diff(g.offsets)
+    rng = np.random.default_rng(400 + k)
+    inside = np.nonzero(pv)[0]
+    verts = np.unique(np.concatenate([rng.choice(np.nonzero(deg <= 300)[0], 300, replace=False),
+                                      inside[deg[inside] <= 300][:300]]))
+    assert np.array_equal(pv[verts], orc.vertex_cliques(g, k, verts, nthreads=16))
