@@ -163,3 +163,54 @@ def test_full_c3_totals_and_samples(arb, orc, c3, k):
     verts = np.unique(np.concatenate([rng.choice(np.nonzero(deg <= 300)[0], 300, replace=False),
                                       inside[deg[inside] <= 300][:300]]))
     assert np.array_equal(pv[verts], orc.vertex_cliques(g, k, verts, nthreads=16))
+
+
+def test_full_c4_batch_learned_in_one_graph(arb):
+    """The batch of 256 graphs of uneven size (10^4..5*10^5 edges; G(n,p), R-MAT scales
+    12-18, 2-D random geometric) as one disjoint union: per-graph orientation, features,
+    and learned-schedule counts for k = 4, 5 captured in one hipGraph; every graph's
+    total against the oracle's, eagerly and on replays."""
+    from paper_2002_10047_amd import learn
+    say("generating the 256-graph batch")
+    gs = gg.batch_mix(256)
+    ref = golden_totals("c4")
+    assert ref["n"] == [g.n for g in gs] and ref["m"] == [g.m for g in gs]
+    u, vo_h = gg.disjoint_union(gs)
+    off, idx = arb.to_device_csr(u)
+    vo = torch.from_numpy(vo_h).cuda()
+    max_n = int(np.diff(vo_h).max())
+    G = len(gs)
+    ks = (4, 5)
+    o = arb.arb_orient_batch(off, idx, vo, max_graph_n=max_n, validate=True)
+    w = {k: learn.load_weights(k) for k in ks}
+    ws = {k: arb._ws(arb.arb_count_batch_workspace(u.n, u.m, k, G), "cuda") for k in ks}
+    tots = {k: torch.empty(G, dtype=torch.int64, device="cuda") for k in ks}
+
+    def pipeline(stream=None):
+        og = arb.arb_orient_batch(off, idx, vo, max_graph_n=max_n, stream=stream)
+        f = arb.arb_features(og["ooff"], og["oidx"], og["round"], og["rank"], stream=stream)
+        for k in ks:
+            op = arb.count_opts(schedule=arb.ARB_SCHED_LEARNED, mlp_weights=w[k], features=f)
+            arb.arb_count_batch_async(og["ooff"], og["oidx"], vo, k, totals=tots[k], opts=op, ws=ws[k],
+                                      stream=stream)
+        return og, f
+
+    keep = pipeline()
+    torch.cuda.synchronize()
+    for k in ks:
+        assert [int(x) for x in arb.u64_numpy(tots[k])] == ref["totals"][str(k)], k
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        keep = pipeline(torch.cuda.current_stream())
+    for rep in range(2):
+        for k in ks:
+            tots[k].fill_(0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in ks:
+            assert [int(x) for x in arb.u64_numpy(tots[k])] == ref["totals"][str(k)], (k, rep)
+    del keep
