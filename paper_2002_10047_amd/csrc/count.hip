@@ -69,7 +69,8 @@ __global__ void k_finish(const int32_t *err, unsigned long long *total) {
 // a split root stay in the root's tier (|S| <= d+(root)); roots too large for any tier
 // are always split and use the largest tier.
 
-constexpr uint32_t kCostMax = (1u << 28) - 1;
+constexpr int kCostBits = 13;                 // schedule key: tier (3 bits) above the cost
+constexpr uint32_t kCostMax = (1u << kCostBits) - 1;
 constexpr int kDeadTier = 7;
 constexpr int kMaxParts = 64;
 
@@ -96,7 +97,7 @@ __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *l
         uint32_t kk;
         int P = 0;
         if (d < k - 1) {
-            kk = ((uint32_t)kDeadTier << 28) | kCostMax;
+            kk = ((uint32_t)kDeadTier << kCostBits) | kCostMax;
         } else {
             int t = tier_of(d);
             if (t < 0) {                       // per-out-neighbour items in the largest tier
@@ -106,9 +107,11 @@ __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *l
                 P = root_parts(d, split_deg, lcost, split_cost, v);
             }
             const float per = P > 0 ? (float)P : (float)d;
-            float c = lcost ? fmaxf(lcost[v] - log2f(per), 0.f) * 4096.f : (float)d / per;
+            // degree cost: out-degree per item; learned: predicted log2 work per item in
+            // steps of 1/64
+            float c = lcost ? fmaxf(lcost[v] - log2f(per), 0.f) * 64.f : (float)d / per;
             uint32_t cq = (uint32_t)fminf(c, (float)kCostMax);
-            kk = ((uint32_t)t << 28) | (kCostMax - cq);
+            kk = ((uint32_t)t << kCostBits) | (kCostMax - cq);
         }
         key[v] = kk;
         val[v] = (int32_t)v;
@@ -121,7 +124,7 @@ __global__ void k_sorted_units(int64_t n, const int64_t *off, const uint32_t *ke
                                const int32_t *parts, int64_t *ucnt) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         int64_t u = 0;
-        if ((key[p] >> 28) != (uint32_t)kDeadTier) {
+        if ((key[p] >> kCostBits) != (uint32_t)kDeadTier) {
             const int32_t v = val[p];
             const int P = parts[v];
             u = P > 0 ? P : off[v + 1] - off[v];
@@ -130,29 +133,45 @@ __global__ void k_sorted_units(int64_t n, const int64_t *off, const uint32_t *ke
     }
 }
 
+// item i of the root v with P parts (P == 1 whole root, P > 1 parts, else one item per
+// out-neighbour)
+__device__ __forceinline__ void put_item(const int64_t *off, const int32_t *idx, int32_t *iroot, int32_t *ichild,
+                                         int64_t at, int32_t v, int P, int64_t i) {
+    iroot[at] = v;
+    ichild[at] = P == 1 ? -1 : (P > 1 ? (int32_t)(-2 - (i * 128 + P)) : idx[off[v] + i]);
+}
+
+// Writes the items of every sorted root: a lane per root, and the whole wave for the
+// roots with more than a few items.
 __global__ void k_expand(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *val, const int32_t *parts,
                          const int64_t *uoff, int32_t *iroot, int32_t *ichild) {
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t p = wave; p < n; p += nwaves) {
-        const int64_t b = uoff[p], c = uoff[p + 1] - b;
-        if (c == 0) continue;
-        const int32_t v = val[p];
-        const int P = parts[v];
-        if (P == 1) {
-            if (lane == 0) { iroot[b] = v; ichild[b] = -1; }
-        } else if (P > 1) {
-            for (int i = lane; i < P; i += 64) {
-                iroot[b + i] = v;
-                ichild[b + i] = -2 - (i * 128 + P);
+    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+        const int64_t p = base + lane;
+        int64_t b = 0, c = 0;
+        int32_t v = 0;
+        int P = 0;
+        if (p < n) {
+            b = uoff[p];
+            c = uoff[p + 1] - b;
+            if (c) {
+                v = val[p];
+                P = parts[v];
             }
-        } else {
-            const int64_t s = off[v];
-            for (int64_t i = lane; i < c; i += 64) {
-                iroot[b + i] = v;
-                ichild[b + i] = idx[s + i];
-            }
+        }
+        const bool big = c > 4;
+        if (!big)
+            for (int64_t i = 0; i < c; ++i) put_item(off, idx, iroot, ichild, b + i, v, P, i);
+        uint64_t m = __ballot(big);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int64_t bb = __shfl(b, src, 64), cc = __shfl(c, src, 64);
+            const int32_t vv = __shfl(v, src, 64);
+            const int PP = __shfl(P, src, 64);
+            for (int64_t i = lane; i < cc; i += 64) put_item(off, idx, iroot, ichild, bb + i, vv, PP, i);
         }
     }
 }
@@ -160,8 +179,8 @@ __global__ void k_expand(int64_t n, const int64_t *off, const int32_t *idx, cons
 // seg[t] = first item of tier t (t = 0..8); items of dead roots are none.
 __global__ void k_segments(int64_t n, const uint32_t *key, const int64_t *uoff, int64_t *seg) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const int t = (int)(key[p] >> 28);
-        const int tp = p > 0 ? (int)(key[p - 1] >> 28) : -1;
+        const int t = (int)(key[p] >> kCostBits);
+        const int tp = p > 0 ? (int)(key[p - 1] >> kCostBits) : -1;
         for (int tt = tp + 1; tt <= t; ++tt) seg[tt] = uoff[p];
         if (p == n - 1)
             for (int tt = t + 1; tt <= 8; ++tt) seg[tt] = uoff[n];
@@ -204,7 +223,7 @@ static size_t carve_count(Carver &c, int64_t n, int64_t m, CountWs *w) {
 }
 
 // learned cost (mlp.hip): predicted log2(1 + work) per root
-int learned_cost(const arb_ocsr *dg, const uint16_t *w, const float *feat, float *cost, hipStream_t s);
+int learned_cost(const arb_ocsr *dg, int k, const uint16_t *w, const float *feat, float *cost, hipStream_t s);
 
 // Optional launch timing: while enabled, every counting-kernel launch is bracketed by
 // two HIP events on the stream it runs on; arb_profile_read folds the pending pairs into
@@ -395,18 +414,18 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     const bool learned = opts.schedule == ARB_SCHED_LEARNED && !work;
     const float *lcost = nullptr;
     if (learned) {
-        if ((rc = learned_cost(dg, opts.mlp_weights, opts.features, w.lcost, s))) return rc;
+        if ((rc = learned_cost(dg, k, opts.mlp_weights, opts.features, w.lcost, s))) return rc;
         lcost = w.lcost;
     }
     const int split_deg = work ? 0 : opts.split_min_degree;
     const float split_cost = work ? 0.f : opts.split_min_cost;
     k_root_keys<<<gb, 256, 0, s>>>(n, dg->offsets, k, lcost, split_deg, split_cost, w.key, w.val, w.parts);
     ARB_CHECK_LAUNCH();
-    if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, n, 31, w.radix_ws, s))) return rc;
+    if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, n, kCostBits + 3, w.radix_ws, s))) return rc;
     k_sorted_units<<<gb, 256, 0, s>>>(n, dg->offsets, w.key, w.val, w.parts, w.ucnt);
     ARB_CHECK_LAUNCH();
     if ((rc = exclusive_scan_i64(w.ucnt, w.ucnt, n, w.scan_ws, s))) return rc;
-    k_expand<<<grid_for(n * 64, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, w.val, w.parts, w.ucnt,
+    k_expand<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, dg->offsets, dg->indices, w.val, w.parts, w.ucnt,
                                                          w.iroot, w.ichild);
     ARB_CHECK_LAUNCH();
     k_segments<<<gb, 256, 0, s>>>(n, w.key, w.ucnt, w.seg);

@@ -28,20 +28,40 @@ __device__ __forceinline__ void load_weights(const uint16_t *wb, float *W) {
 
 // ------------------------------------------------------------------ features
 
+// A lane per row; rows with more than 32 out-neighbours are summed by the whole wave.
 __global__ void k_feat_rows(int64_t n, const int64_t *off, const int32_t *idx, float *feat) {
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r = wave; r < n; r += nwaves) {
-        const int64_t s = off[r], e = off[r + 1];
-        int64_t sum = 0;
-        for (int64_t p = s + lane; p < e; p += 64) {
-            const int32_t u = idx[p];
-            sum += off[u + 1] - off[u];
+    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+        const int64_t r = base + lane;
+        int64_t s = 0, e = 0;
+        if (r < n) {
+            s = off[r];
+            e = off[r + 1];
         }
+        const bool big = e - s > 32;
+        int64_t sum = 0;
+        if (!big)
+            for (int64_t p = s; p < e; ++p) {
+                const int32_t u = idx[p];
+                sum += off[u + 1] - off[u];
+            }
+        uint64_t m = __ballot(big);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int64_t ss = __shfl(s, src, 64), ee = __shfl(e, src, 64);
+            int64_t part = 0;
+            for (int64_t p = ss + lane; p < ee; p += 64) {
+                const int32_t u = idx[p];
+                part += off[u + 1] - off[u];
+            }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        if (lane == 0) {
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+            if (lane == src) sum = part;
+        }
+        if (r < n) {
             feat[3 * r + 0] = log2f(1.0f + (float)(e - s));
             feat[3 * r + 1] = log2f(1.0f + (float)sum);
         }
@@ -106,22 +126,26 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const uint16_t *wb, const float
 // H'^T is exactly the B operand of block kb = nb for the next layer.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16v4 __attribute__((ext_vector_type(4)));
 
+// hi = rne(h), lo = rne(h - hi) with the packed hardware conversion
 __device__ __forceinline__ void split_bf16(const f32x4 h, bf16x4 &hi, bf16x4 &lo) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const uint16_t a = f32_to_bf16(h[e]);
-        hi[e] = (short)a;
-        lo[e] = (short)f32_to_bf16(h[e] - bf16_to_f32(a));
-    }
+    const bf16v4 a = __builtin_convertvector(h, bf16v4);
+    const bf16v4 b = __builtin_convertvector(h - __builtin_convertvector(a, f32x4), bf16v4);
+    hi = __builtin_bit_cast(bf16x4, a);
+    lo = __builtin_bit_cast(bf16x4, b);
 }
 
-__global__ void __launch_bounds__(256) k_mlp_fwd_mfma(const uint16_t *wb, const float *x, int64_t rows, float *y) {
+// With off != nullptr (the schedule's use), tiles whose 16 roots all have fewer than
+// dmin out-neighbours (roots the count drops) are skipped; their y stays unset.
+__global__ void __launch_bounds__(256) k_mlp_fwd_mfma(const uint16_t *wb, const float *x, int64_t rows, float *y,
+                                                       const int64_t *off, int64_t dmin) {
     __shared__ float W[NP];
     load_weights(wb, W);
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, q = lane >> 4;
     // A operands of layers 2 and 3: W[nb*16 + r16][kb*16 + 4q .. +3]
+    // (from the block's float copy: exact, the weights are bf16 values)
     bf16x4 A2[4][4], A3[4][4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
@@ -130,8 +154,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(const uint16_t *wb, const 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int o = (nb * 16 + r16) * H + kb * 16 + 4 * q + e;
-                A2[nb][kb][e] = (short)wb[oW2 + o];
-                A3[nb][kb][e] = (short)wb[oW3 + o];
+                A2[nb][kb][e] = (short)f32_to_bf16(W[oW2 + o]);
+                A3[nb][kb][e] = (short)f32_to_bf16(W[oW3 + o]);
             }
     const int64_t tiles = (rows + 15) / 16;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -139,6 +163,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(const uint16_t *wb, const 
     for (int64_t t = wave; t < tiles; t += nwaves) {
         const int64_t r = t * 16 + r16;
         const bool live = r < rows;
+        if (off && !__any(live && off[r + 1] - off[r] >= dmin)) continue;
         const float x0 = live ? x[3 * r] : 0.f, x1 = live ? x[3 * r + 1] : 0.f, x2 = live ? x[3 * r + 2] : 0.f;
         // layer 1 (VALU) straight into B layout: units kb*16 + 4q + e of row r
         bf16x4 Bhi[4], Blo[4];
@@ -346,9 +371,10 @@ __global__ void k_to_bf16(const float *w, uint16_t *wb, int64_t n) {
         wb[p] = f32_to_bf16(w[p]);
 }
 
-int learned_cost(const arb_ocsr *dg, const uint16_t *w, const float *feat, float *cost, hipStream_t s) {
+int learned_cost(const arb_ocsr *dg, int k, const uint16_t *w, const float *feat, float *cost, hipStream_t s) {
     if (dg->n == 0) return ARB_OK;
-    k_mlp_fwd_mfma<<<grid_for((dg->n + 15) / 16 * 64, 256, 2048), 256, 0, s>>>(w, feat, dg->n, cost);
+    k_mlp_fwd_mfma<<<grid_for((dg->n + 15) / 16 * 64, 256, 512), 256, 0, s>>>(w, feat, dg->n, cost, dg->offsets,
+                                                                               (int64_t)(k - 1));
     ARB_CHECK_LAUNCH();
     return ARB_OK;
 }
@@ -366,7 +392,7 @@ extern "C" int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const
     }
     const int64_t n = dg->n;
     if (n > 0) {
-        k_feat_rows<<<grid_for(n * 64, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, feat);
+        k_feat_rows<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, dg->offsets, dg->indices, feat);
         if (rank) k_feat_round<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, round_orig, rank, feat);
         else k_feat_round<<<1, 64, 0, s>>>(0, nullptr, nullptr, feat);
         if (hipGetLastError() != hipSuccess) { set_error(ARB_EHIP); return ARB_EHIP; }
@@ -382,8 +408,8 @@ extern "C" int arb_mlp_forward(const uint16_t *w_bf16, const float *x, int64_t r
         if (act)
             k_mlp_fwd<<<grid_for(rows, 256, 4096), 256, 0, as_stream(stream)>>>(w_bf16, x, rows, y, act);
         else
-            k_mlp_fwd_mfma<<<grid_for((rows + 15) / 16 * 64, 256, 2048), 256, 0, as_stream(stream)>>>(w_bf16, x, rows,
-                                                                                                     y);
+            k_mlp_fwd_mfma<<<grid_for((rows + 15) / 16 * 64, 256, 512), 256, 0, as_stream(stream)>>>(w_bf16, x, rows,
+                                                                                                    y, nullptr, 0);
         if (hipGetLastError() != hipSuccess) { set_error(ARB_EHIP); return ARB_EHIP; }
     }
     set_error(ARB_OK);
