@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
 # plain 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# LDS: 128 B/clk/CU (the CDNA3 figure) x 256 CUs x 2.4 GHz; the probe's measurement is
+# used when larger
+SPEC_LDS_GBS = 128 * 256 * 2.4e9 / 1e9
 
 
 def log(*a):
@@ -63,7 +66,7 @@ def algorithmic_units(arb, o, ks, np):
     gather = np.bincount(rows, weights=d[oidx].astype(np.float64), minlength=n).astype(np.int64)
     W = (d + 31) // 32
     nodes = {}
-    for k in sorted(set(ks) | {3}):
+    for k in sorted(set(ks) | {k - 1 for k in ks if k >= 4} | {3}):
         work = torch.empty(n, dtype=torch.int64, device="cuda")
         total = torch.empty(1, dtype=torch.int64, device="cuda")
         arb.arb_count_async(o["ooff"], o["oidx"], k, total=total, work=work)
@@ -145,6 +148,34 @@ def copy_calibration(a, torch):
     dst.copy_(src)
     torch.cuda.synchronize()
     log(f"copy calibration: {nb} bytes read and {nb} bytes written once")
+
+
+def measure_peaks(torch):
+    """LDS read and device copy bandwidth from the project's probes (libarb_probe.so)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2002_10047_amd", "libarb_probe.so"))
+    lib.arb_probe_lds_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+    lib.arb_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_void_p]
+    props = torch.cuda.get_device_properties(0)
+    cus = props.multi_processor_count
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    scratch = torch.empty(cus * 2 * 1024, dtype=torch.int32, device="cuda")
+    lds = []
+    for bpc in (1, 2):
+        v = ctypes.c_double(0.0)
+        if lib.arb_probe_lds_read(ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), bpc, ctypes.byref(v),
+                                  stream) == 0:
+            lds.append(v.value / 1e9)
+    nb = 1 << 30
+    src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    v = ctypes.c_double(0.0)
+    cp = v.value / 1e9 if lib.arb_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb, 5,
+                                             ctypes.byref(v), stream) == 0 else None
+    del src, dst
+    return {"lds_read_GBs": max(lds) if lds else None, "copy_GBs": cp if cp else None, "cus": cus}
 
 
 def kernel_source_hash():
@@ -315,45 +346,72 @@ def main():
     d, W, gather, nodes = algorithmic_units(arb, o, ks, np)
     tw = [2, 4, 8, 12, 16, 24]
     per_sym = {}
+    phase_units = {}            # per k: algorithmic units of one count (all tiers)
+    peaks = measure_peaks(torch)
+    peak_lds = max(SPEC_LDS_GBS, peaks["lds_read_GBs"] or 0.0)
+    log(f"probes: LDS read {peaks['lds_read_GBs']:.0f} GB/s, device copy {peaks['copy_GBs']:.0f} GB/s "
+        f"(LDS peak used {peak_lds:.0f} GB/s)")
     for e in prof:
         k, ti = e["k"], e["tier"]
         live = d >= k - 1
         sel = live & (tier_of(d) == ti)
         hbm_bytes = float(4 * (d[sel] + 4 * d[sel] + gather[sel]).sum() + 16 * sel.sum())
-        alu_ops = 0.0
+        alu_ops = lds_bytes = 0.0
         if k >= 4:
             ck2 = nodes[k][sel] - nodes[k - 1][sel]          # c_{k-2}(v)
             deep = nodes[k][sel] - d[sel]                    # sum_{j=2}^{k-2} c_j(v)
             # every node of depth >= 2 ANDs W words; nodes of depth k-2 also popcount them
             alu_ops = float((W[sel] * (deep + ck2)).sum())
+            # bit rows built (d), a row read and I' written per internal node (depth
+            # 1..k-3), a row read per node of depth k-2: 4 W (d + 2 sum_{j<=k-3} c_j + c_{k-2})
+            lds_bytes = float((4 * W[sel] * (d[sel] + nodes[k - 1][sel] + nodes[k][sel])).sum())
         sym = f"k_count<{tw[ti]},{max(1, k - 3)},0,0>"
-        s_ = per_sym.setdefault(sym, dict(launches=0, ms=0.0, hbm=0.0, alu=0.0, parts=[]))
+        s_ = per_sym.setdefault(sym, dict(launches=0, ms=0.0, hbm=0.0, alu=0.0, lds=0.0, parts=[]))
         s_["launches"] += e["launches"]
         s_["ms"] += e["total_ms"]
         s_["hbm"] += e["launches"] * hbm_bytes
         s_["alu"] += e["launches"] * alu_ops
+        s_["lds"] += e["launches"] * lds_bytes
+        pk = phase_units.setdefault(k, dict(alu=0.0, lds=0.0, hbm=0.0))
+        pk["alu"] += alu_ops
+        pk["lds"] += lds_bytes
+        pk["hbm"] += hbm_bytes
         s_["parts"].append(f"k={k}: {e['launches']} launches, {e['total_ms'] / e['launches']:.3f} ms avg")
     best = None
     for sym, v in sorted(per_sym.items()):
         sec = v["ms"] / 1e3
         hbm = v["hbm"] / sec / 1e9
         alu = v["alu"] / sec / 1e12
+        lds = v["lds"] / sec / 1e9
         log(f"  {sym}: {v['launches']} launches, avg {v['ms'] / v['launches']:.3f} ms ({'; '.join(v['parts'])}), "
-            f"algorithmic {hbm:.0f} GB/s ({hbm / PEAK_HBM_GBS:.2%} of HBM), {alu:.2f} Tops ({alu / PEAK_ALU_TOPS:.2%} of ALU)")
+            f"algorithmic {hbm:.0f} GB/s ({hbm / PEAK_HBM_GBS:.2%} of HBM), {alu:.2f} Tops ({alu / PEAK_ALU_TOPS:.2%} "
+            f"of ALU), LDS {lds:.0f} GB/s ({lds / peak_lds:.2%})")
         if best is None or v["ms"] > best[1]["ms"]:
-            best = (sym, v, hbm, alu)
+            best = (sym, v, hbm, alu, lds)
     if best:
-        sym, v, hbm, alu = best
-        fr_h, fr_a = hbm / PEAK_HBM_GBS, alu / PEAK_ALU_TOPS
-        if fr_a >= fr_h:
-            out["roofline"] = {"bound": "alu", "achieved": alu, "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "frac": fr_a}
-        else:
-            out["roofline"] = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": fr_h}
+        sym, v, hbm, alu, lds = best
+        fr = {"hbm": hbm / PEAK_HBM_GBS, "alu": alu / PEAK_ALU_TOPS, "lds": lds / peak_lds}
+        bound = max(fr, key=fr.get)
+        unit = {"hbm": ("GB/s", hbm, PEAK_HBM_GBS), "alu": ("Tops/s", alu, PEAK_ALU_TOPS),
+                "lds": ("GB/s", lds, peak_lds)}[bound]
+        out["roofline"] = {"bound": bound, "achieved": unit[1], "peak": unit[2], "unit": unit[0], "frac": fr[bound]}
         out["roofline"]["traffic"] = measured_traffic(sym)
         out["roofline"]["kernel"] = sym
         out["roofline"]["launches"] = v["launches"]
         out["roofline"]["launch_ms"] = v["ms"] / v["launches"]
-        out["roofline"]["algorithmic_per_launch"] = (v["alu"] if fr_a >= fr_h else v["hbm"]) / v["launches"]
+        out["roofline"]["algorithmic_per_launch"] = {"hbm": v["hbm"], "alu": v["alu"], "lds": v["lds"]}[bound] / \
+            v["launches"]
+        out["roofline"]["fracs"] = fr
+        out["roofline"]["lds_words_per_s"] = lds * 1e9 / 4
+        out["roofline"]["peaks_measured"] = peaks
+    # whole count of each k (all tier kernels, concurrent): algorithmic rates over its time
+    for k, u in phase_units.items():
+        if str(k) in per_k:
+            t = per_k[str(k)]["count_s"]
+            per_k[str(k)]["alu_Tops"] = u["alu"] / t / 1e12
+            per_k[str(k)]["alu_frac"] = u["alu"] / t / 1e12 / PEAK_ALU_TOPS
+            per_k[str(k)]["lds_GBs"] = u["lds"] / t / 1e9
+            per_k[str(k)]["hbm_GBs"] = u["hbm"] / t / 1e9
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:

@@ -9,6 +9,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libarb.so")
+PROBE_OUT = os.path.join(HERE, "libarb_probe.so")
+PROBE_SOURCES = ["peaks.hip"]
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["prims.hip", "orient.hip", "count.hip", "mlp.hip", "abi.hip"] + [f"count_d{i}.hip" for i in range(1, 8)]
 FLAGS = [
@@ -43,6 +45,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, OUT)
+    # roofline probes: a library of their own, loaded only by bench.py
+    pobjs = [compile_one(src) for src in PROBE_SOURCES]
+    r = subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", PROBE_OUT + ".tmp", *pobjs],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
+    os.replace(PROBE_OUT + ".tmp", PROBE_OUT)
     return OUT
 
 
