@@ -71,6 +71,7 @@ __global__ void k_finish(const int32_t *err, unsigned long long *total) {
 
 constexpr int kCostBits = 13;                 // schedule key: tier (3 bits) above the cost
 constexpr uint32_t kCostMax = (1u << kCostBits) - 1;
+constexpr int kBigTier = kNumTiers;        // roots above the LDS tiers (k = 3, 4)
 constexpr int kDeadTier = 7;
 constexpr int kMaxParts = 64;
 
@@ -91,7 +92,7 @@ __device__ __forceinline__ int root_parts(int64_t d, int split_deg, const float 
 }
 
 __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *lcost, int split_deg, float split_cost,
-                            uint32_t *key, int32_t *val, int32_t *parts) {
+                            int dbig, uint32_t *key, int32_t *val, int32_t *parts) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = off[v + 1] - off[v];
         uint32_t kk;
@@ -100,7 +101,10 @@ __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *l
             kk = ((uint32_t)kDeadTier << kCostBits) | kCostMax;
         } else {
             int t = tier_of(d);
-            if (t < 0) {                       // per-out-neighbour items in the largest tier
+            if (t < 0 && (k == 3 || k == 4) && d <= dbig) {
+                t = kBigTier;                  // whole root, bit rows in global scratch
+                P = 1;
+            } else if (t < 0) {                // per-out-neighbour items in the largest tier
                 t = kNumTiers - 1;
                 P = -1;
             } else {
@@ -198,10 +202,13 @@ struct CountWs {
     int32_t *parts;       // n
     float *lcost;         // n
     unsigned long long *tot;  // total of the synchronous arb_count
+    uint32_t *big_rows;       // big-root bit rows: big_teams slices of big_words words
+    int64_t big_teams, big_words;
+    int dbig;
     void *scan_ws, *radix_ws;
 };
 
-static size_t carve_count(Carver &c, int64_t n, int64_t m, CountWs *w) {
+static size_t carve_count(Carver &c, int64_t n, int64_t m, int k, CountWs *w) {
     const int64_t nn = n > 0 ? n : 1;
     const int64_t U = nn + (m > 0 ? m : 1);
     w->ucnt = c.take<int64_t>(nn + 1);
@@ -219,6 +226,10 @@ static size_t carve_count(Carver &c, int64_t n, int64_t m, CountWs *w) {
     w->tot = c.take<unsigned long long>(4);
     w->scan_ws = c.take<char>(scan_workspace(nn + 1));
     w->radix_ws = c.take<char>(radix_workspace(nn));
+    w->dbig = (k == 3 || k == 4) ? big_dmax(m) : 0;
+    w->big_teams = w->dbig ? big_teams(m) : 0;
+    w->big_words = w->dbig ? big_team_words(w->dbig) : 0;
+    w->big_rows = c.take<uint32_t>(w->big_teams * w->big_words > 0 ? w->big_teams * w->big_words : 1);
     return c.used;
 }
 
@@ -340,7 +351,7 @@ extern "C" size_t arb_count_workspace(int64_t n, int64_t m, int k) {
     (void)k;
     Carver c(nullptr);
     CountWs w;
-    return carve_count(c, n, m, &w) + 256;
+    return carve_count(c, n, m, k, &w) + 256;
 }
 
 static bool ocsr_ok(const arb_ocsr *dg) {
@@ -406,7 +417,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
 
     Carver cv(ws);
     CountWs w;
-    carve_count(cv, n, m, &w);
+    carve_count(cv, n, m, k, &w);
     if ((rc = fill_i32(w.err, 0, 4, s))) return rc;
     if ((rc = fill_i32(w.heads, 0, 16, s))) return rc;
     if ((rc = fill_i64(w.seg, 0, 16, s))) return rc;
@@ -419,7 +430,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     }
     const int split_deg = work ? 0 : opts.split_min_degree;
     const float split_cost = work ? 0.f : opts.split_min_cost;
-    k_root_keys<<<gb, 256, 0, s>>>(n, dg->offsets, k, lcost, split_deg, split_cost, w.key, w.val, w.parts);
+    k_root_keys<<<gb, 256, 0, s>>>(n, dg->offsets, k, lcost, split_deg, split_cost, w.dbig, w.key, w.val, w.parts);
     ARB_CHECK_LAUNCH();
     if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, n, kCostBits + 3, w.radix_ws, s))) return rc;
     k_sorted_units<<<gb, 256, 0, s>>>(n, dg->offsets, w.key, w.val, w.parts, w.ucnt);
@@ -501,6 +512,40 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
             ARB_HIP(hipStreamWaitEvent(s, g_ts.join[t], 0));
         }
     }
+    if (w.big_teams > 0) {
+        // roots above the LDS tiers, after the tier kernels (joined into s above)
+        CountArgs a;
+        a.off = dg->offsets;
+        a.idx = dg->indices;
+        a.n = n;
+        a.m = m;
+        a.k = k;
+        a.item_root = w.iroot;
+        a.item_child = w.ichild;
+        a.seg = w.seg + kBigTier;
+        a.head = w.heads + kBigTier;
+        a.total = total;
+        a.pv = pv;
+        a.per_root = per_root;
+        a.work = work;
+        a.err = w.err;
+        a.chunk = 1;
+        a.span_max = 0;
+        a.persistent = 1;
+        a.one_item_per_team = 0;
+        const BigArgs b{w.big_rows, w.big_words, w.dbig};
+        const unsigned grid = (unsigned)(w.big_teams < cus ? w.big_teams : cus);
+        ProfPending pp{ProfKey{kBigTier, k, pvm ? 1 : 0, instr ? 1 : 0}, nullptr, nullptr};
+        if (prof) {
+            if ((rc = prof_event(&pp.a)) || (rc = prof_event(&pp.b))) return rc;
+            ARB_HIP(hipEventRecord(pp.a, s));
+        }
+        if ((rc = launch_count_big(pvm, instr, a, b, grid, s))) return rc;
+        if (prof) {
+            ARB_HIP(hipEventRecord(pp.b, s));
+            g_prof.pending.push_back(pp);
+        }
+    }
     k_finish<<<1, 64, 0, s>>>(w.err, total);
     ARB_CHECK_LAUNCH();
     return ARB_OK;
@@ -522,7 +567,7 @@ extern "C" uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex, c
     if (arb_check_oriented(dg, ws, ws_bytes, stream)) return 0;
     Carver cv(ws);
     CountWs w;
-    carve_count(cv, dg->n, dg->m, &w);
+    carve_count(cv, dg->n, dg->m, k, &w);
     int rc = count_impl(dg, k, reinterpret_cast<uint64_t *>(w.tot), per_vertex, nullptr, nullptr, opts, ws, ws_bytes, s);
     if (rc) { set_error(rc); return 0; }
     uint64_t h = 0;
@@ -600,7 +645,7 @@ extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int
     if (ws_bytes < arb_count_workspace(dg->n, dg->m, k)) return fail(ARB_EWORKSPACE);
     Carver cv(ws);
     CountWs w;
-    carve_count(cv, dg->n, dg->m, &w);
+    carve_count(cv, dg->n, dg->m, k, &w);
     uint64_t *tot = reinterpret_cast<uint64_t *>(w.tot);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ARB_EHIP);

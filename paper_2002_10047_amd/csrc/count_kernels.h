@@ -860,6 +860,33 @@ inline size_t tier_block_lds(int tier, bool pv, int lmax) {
     }
 }
 
+// Roots with more than ARB_MAX_LOCAL out-neighbours at k = 3, 4 (count_big.hip): one
+// 16-wave team per root, S and its hash in LDS, the bit rows of G[S] in a per-team slice
+// of global scratch (L2-resident), up to kBigMax out-neighbours.
+constexpr int kBigMax = 4096;
+struct BigArgs {
+    uint32_t *rows;        // scratch: teams x team_words words
+    int64_t team_words;
+    int dbig;              // roots with ARB_MAX_LOCAL < d+ <= dbig take this path
+};
+
+// Largest out-degree the peel can produce on m edges: d(d+1) <= 2(2+eps)m, so at eps = 1
+// d < sqrt(6m) (larger eps: such roots fall back to per-out-neighbour items).
+inline int big_dmax(int64_t m) {
+    double r = 1.0;
+    while (r * r < 6.0 * (double)m && r < kBigMax) r += 1.0;
+    const int d = (int)r;
+    return d > ARB_MAX_LOCAL ? (d < kBigMax ? d : kBigMax) : 0;
+}
+// at most m / (ARB_MAX_LOCAL + 1) roots can be that large
+inline int64_t big_teams(int64_t m) {
+    const int64_t t = m / (ARB_MAX_LOCAL + 1);
+    return big_dmax(m) == 0 ? 0 : (t < 1 ? 1 : (t > 256 ? 256 : t));
+}
+inline int64_t big_team_words(int dbig) { return (int64_t)dbig * ((dbig + 31) / 32); }
+
+int launch_count_big(bool pv, bool instr, const CountArgs &a, const BigArgs &b, unsigned grid, hipStream_t s);
+
 #define ARB_DECLARE_DEPTH(LM) \
     int launch_count_depth##LM(int tier, bool pv, bool instr, const CountArgs &a, unsigned grid, hipStream_t s);
 ARB_DECLARE_DEPTH(1)

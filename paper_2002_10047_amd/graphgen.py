@@ -192,6 +192,120 @@ def rmat(scale: int, nsamples: int, a: float = 0.57, b: float = 0.19, c: float =
     return csr_from_pairs(n, u, v, f"rmat(scale={scale},samples={nsamples},seed={seed})")
 
 
+def rmat_device(scale: int, nsamples: int, a: float = 0.57, b: float = 0.19, c: float = 0.19, seed: int = 51,
+                device="cuda", chunk: int = 1 << 24):
+    """R-MAT as in rmat(), generated on the GPU with torch's seeded device generator (for
+    graphs too large to build on the host in test time): (n, offsets int64[n+1], indices
+    int32[2m]) as device tensors, rows sorted, simple and symmetric.  The random stream
+    is torch's, so the graph differs from rmat() with the same seed."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    n = 1 << scale
+    perm = torch.randperm(n, generator=gen, device=device)
+    keys = []
+    left = nsamples
+    while left > 0:
+        cnt = min(chunk, left)
+        left -= cnt
+        u = torch.zeros(cnt, dtype=torch.int64, device=device)
+        v = torch.zeros(cnt, dtype=torch.int64, device=device)
+        for lvl in range(scale):
+            r = torch.rand(cnt, generator=gen, device=device, dtype=torch.float64)
+            bit = 1 << (scale - 1 - lvl)
+            u |= (r >= a + b).to(torch.int64) * bit
+            v |= (((r >= a) & (r < a + b)) | (r >= a + b + c)).to(torch.int64) * bit
+        u = perm[u]
+        v = perm[v]
+        keep = u != v
+        u, v = u[keep], v[keep]
+        keys.append((torch.minimum(u, v) << scale) | torch.maximum(u, v))
+        del u, v, keep
+    key = torch.unique(torch.cat(keys))           # sorted, one entry per undirected edge
+    del keys
+    off, idx = _device_csr_from_keys(key, scale, n)
+    return n, off, idx
+
+
+def _device_csr_from_keys(key, bits: int, n: int):
+    """CSR (offsets int64[n+1], indices int32[2m]) on key's device from sorted unique keys
+    lo << bits | hi, lo < hi: row r lists its neighbours below r, then those above r."""
+    import torch
+    device = key.device
+    lo = key >> bits
+    hi = key & ((1 << bits) - 1)
+    m = lo.numel()
+    deg_up = torch.bincount(lo, minlength=n)      # neighbours above each vertex
+    deg_dn = torch.bincount(hi, minlength=n)      # neighbours below
+    off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    off[1:] = torch.cumsum(deg_up + deg_dn, 0)
+    idx = torch.empty(2 * m, dtype=torch.int32, device=device)
+    # row lo, upper part: after its deg_dn lower neighbours, in key order (ascending hi)
+    first_up = torch.cumsum(deg_up, 0) - deg_up
+    idx[off[lo] + deg_dn[lo] + (torch.arange(m, device=device) - first_up[lo])] = hi.to(torch.int32)
+    del first_up
+    # row hi, lower part: neighbours lo in ascending order, at the start of the row
+    k2, _ = torch.sort((hi << bits) | lo)
+    del lo, hi
+    hi2 = k2 >> bits
+    lo2 = k2 & ((1 << bits) - 1)
+    del k2
+    first_dn = torch.cumsum(deg_dn, 0) - deg_dn
+    idx[off[hi2] + (torch.arange(m, device=device) - first_dn[hi2])] = lo2.to(torch.int32)
+    return off, idx
+
+
+def rgg_device(n: int, avg_deg: float = 40.0, seed: int = 52, device="cuda", chunk: int = 1 << 21):
+    """3-D random geometric graph as in rgg(n, 3, avg_deg): n uniform points on the unit
+    torus [0,1)^3, an edge iff the torus distance is at most r = (avg_deg / (4/3 pi n))^(1/3),
+    built on the GPU with a cell list (cells of side >= r, the 27 neighbouring cells of each
+    point's cell searched); torch's seeded device generator, so the graph differs from
+    rgg() with the same seed.  Returns (n, offsets int64[n+1], indices int32[2m])."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    r = (avg_deg / ((4.0 / 3.0) * math.pi * n)) ** (1.0 / 3.0)
+    G = max(3, int(math.floor(1.0 / r)))            # cells per axis, side 1/G >= r
+    pts = torch.rand((n, 3), generator=gen, device=device, dtype=torch.float64)
+    cxyz = torch.clamp((pts * G).to(torch.int64), max=G - 1)
+    cell = (cxyz[:, 0] * G + cxyz[:, 1]) * G + cxyz[:, 2]
+    cell_sorted, order = torch.sort(cell)
+    ncell = G * G * G
+    cstart = torch.zeros(ncell + 1, dtype=torch.int64, device=device)
+    cstart[1:] = torch.cumsum(torch.bincount(cell_sorted, minlength=ncell), 0)
+    kmax = int((cstart[1:] - cstart[:-1]).max())
+    bits = max(1, (n - 1).bit_length())
+    r2 = r * r
+    keys = []
+    for c0 in range(0, n, chunk):
+        ids = order[c0:c0 + chunk]                  # points of this chunk, in cell order
+        p = pts[ids]
+        cx, cy, cz = cxyz[ids, 0], cxyz[ids, 1], cxyz[ids, 2]
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    nc = (((cx + dx) % G) * G + (cy + dy) % G) * G + (cz + dz) % G
+                    s0 = cstart[nc]
+                    cnt = cstart[nc + 1] - s0
+                    for t in range(kmax):
+                        ok = cnt > t
+                        if not bool(ok.any()):
+                            break
+                        src = ids[ok]
+                        dst = order[s0[ok] + t]
+                        keep = src < dst
+                        src, dst = src[keep], dst[keep]
+                        dv = torch.abs(pts[src] - pts[dst])
+                        dv = torch.minimum(dv, 1.0 - dv)
+                        close = (dv * dv).sum(1) <= r2
+                        keys.append((src[close] << bits) | dst[close])
+        del p
+    key = torch.unique(torch.cat(keys))
+    del keys
+    off, idx = _device_csr_from_keys(key, bits, n)
+    return n, off, idx
+
+
 def _capped_weights(n: int, beta: float, total: float, wmax: float) -> np.ndarray:
     w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (beta - 1.0))
     for _ in range(100):

@@ -214,3 +214,97 @@ def test_full_c4_batch_learned_in_one_graph(arb):
         for k in ks:
             assert [int(x) for x in arb.u64_numpy(tots[k])] == ref["totals"][str(k)], (k, rep)
     del keep
+
+
+def _sample_and_check_roots(arb, orc, n, o, pr, k, rng, heavy=30, per_tier=150, rand=1000):
+    ooff = o["ooff"].cpu().numpy()
+    oidx = o["oidx"].cpu().numpy()
+    d = np.diff(ooff)
+    live = np.nonzero(d >= k - 1)[0]
+    pick = [np.argsort(-d)[:heavy], rng.choice(live, min(rand, live.size), replace=False)]
+    for lo, hi in zip([0, 64, 128, 256, 384, 512, 768], [64, 128, 256, 384, 512, 768, 1 << 40]):
+        t = live[(d[live] > lo) & (d[live] <= hi)]
+        if t.size:
+            pick.append(rng.choice(t, min(t.size, per_tier), replace=False))
+    roots = np.unique(np.concatenate(pick))
+    say("k", k, "checking", roots.size, "roots, max d+", int(d[roots].max()))
+    lc = orc.local_cliques_roots(n, ooff, oidx, k - 1, roots, nthreads=16)
+    assert np.array_equal(pr[roots], lc[:, k - 2])
+
+
+def _orientation_properties(arb, o, n, eps=1.0):
+    import math
+    rank = o["rank"]
+    assert torch.equal(torch.sort(rank)[0], torch.arange(n, dtype=rank.dtype, device=rank.device))
+    assert arb.arb_check_oriented(o["ooff"], o["oidx"]) == 0
+    rounds = int(o["stats"][0])
+    assert 1 <= rounds <= math.ceil(math.log(n) / math.log(2.0 + eps))
+    thr = o["stats"][2:2 + rounds]
+    dplus = o["ooff"][1:] - o["ooff"][:-1]                 # rank space
+    assert bool((dplus[rank.long()] <= thr[o["round"].long()]).all())
+
+
+def test_full_c5a_rmat26_k4(arb, orc):
+    """R-MAT scale 26 (2^30 samples, 2^26 vertices, ~1.05 billion edges, built on the GPU):
+    orientation invariants at full size, k = 4 total = sum of per-root counts, per-root
+    counts of the heaviest roots (2926 out-neighbours: the big-root path) and of every
+    tier against the oracle, per-vertex counts of sampled vertices."""
+    say("generating R-MAT scale 26 on the GPU")
+    n, off, idx = gg.rmat_device(26, 1 << 30, seed=51)
+    assert arb.arb_validate(off, idx) == 0
+    o = arb.arb_orient(off, idx, eps=1.0)
+    _orientation_properties(arb, o, n)
+    k = 4
+    ws = arb.CountWorkspace(o["ooff"], o["oidx"], k)
+    per_root = torch.empty(n, dtype=torch.int64, device="cuda")
+    total = torch.empty(1, dtype=torch.int64, device="cuda")
+    arb.arb_count_async(o["ooff"], o["oidx"], k, total=total, per_root=per_root, ws=ws)
+    torch.cuda.synchronize()
+    t = int(arb.u64_numpy(total)[0])
+    pr = arb.u64_numpy(per_root)
+    del per_root
+    assert int(pr.sum(dtype=np.uint64)) == t
+    _sample_and_check_roots(arb, orc, n, o, pr, k, np.random.default_rng(51))
+    tp, pv_rank = arb.arb_count(o["ooff"], o["oidx"], k, per_vertex=True, ws=ws)
+    assert tp == t and int(pv_rank.sum(dtype=np.uint64)) == (4 * t) % (1 << 64)
+    pv = pv_rank[o["rank"].cpu().numpy()]
+    del pv_rank
+    # vertices whose own and whose neighbours' degrees keep the oracle's merges short
+    deg = (off[1:] - off[:-1])
+    nbr_max = torch.zeros(n, dtype=torch.int64, device="cuda")
+    rows = torch.repeat_interleave(torch.arange(n, device="cuda"), deg)
+    nbr_max.scatter_reduce_(0, rows, deg[idx.long()], reduce="amax")
+    del rows
+    ok = torch.nonzero((deg >= 3) & (deg <= 1000) & (nbr_max <= 20000)).squeeze(1).cpu().numpy()
+    verts = np.random.default_rng(52).choice(ok, 300, replace=False)
+    g = gg.Graph(n, off.cpu().numpy(), idx.cpu().numpy())
+    assert np.array_equal(pv[verts], orc.vertex_cliques(g, k, verts, nthreads=16))
+
+
+def test_full_c5b_rgg3d(arb, orc):
+    """3-D random geometric graph, 2^24 points on the unit torus, mean degree 40 (~335M
+    edges, built on the GPU): k = 5, 6, 7 with per-vertex counts; per-root and per-vertex
+    counts of sampled roots / vertices against the oracle; sums against the totals."""
+    say("generating the 3-D random geometric graph on the GPU")
+    n, off, idx = gg.rgg_device(1 << 24, 40.0, seed=52)
+    assert arb.arb_validate(off, idx) == 0
+    o = arb.arb_orient(off, idx, eps=1.0)
+    _orientation_properties(arb, o, n)
+    g = gg.Graph(n, off.cpu().numpy(), idx.cpu().numpy())
+    rank = o["rank"].cpu().numpy()
+    for k in (5, 6, 7):
+        ws = arb.CountWorkspace(o["ooff"], o["oidx"], k)
+        per_root = torch.empty(n, dtype=torch.int64, device="cuda")
+        total = torch.empty(1, dtype=torch.int64, device="cuda")
+        arb.arb_count_async(o["ooff"], o["oidx"], k, total=total, per_root=per_root, ws=ws)
+        torch.cuda.synchronize()
+        t = int(arb.u64_numpy(total)[0])
+        pr = arb.u64_numpy(per_root)
+        del per_root
+        assert int(pr.sum(dtype=np.uint64)) == t
+        _sample_and_check_roots(arb, orc, n, o, pr, k, np.random.default_rng(60 + k), rand=500)
+        tp, pv_rank = arb.arb_count(o["ooff"], o["oidx"], k, per_vertex=True, ws=ws)
+        assert tp == t and int(pv_rank.sum(dtype=np.uint64)) == (k * t) % (1 << 64)
+        verts = np.random.default_rng(70 + k).choice(n, 300, replace=False)
+        assert np.array_equal(pv_rank[rank][verts], orc.vertex_cliques(g, k, verts, nthreads=16)), k
+        say("k", k, "total", t)
