@@ -255,6 +255,21 @@ int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int trials, fl
 
 #define ARB_MLP_PARAMS 8641     /* 3->64->64->64->1, ReLU, weights then bias per layer */
 
+/* Workspace of arb_sparsify. */
+size_t arb_sparsify_workspace(int64_t n, int64_t nnz);
+
+/* Colorful sparsification (Sec. 3.3; estimator and its variance in the appendix's
+ * sampling theorem): keeps the edges {u, v} of g with colors[u] == colors[v] (colors:
+ * device int32[n], drawn by the caller, e.g. uniformly from c colours).  out_offsets
+ * (device, n+1) and out_indices (device, capacity g->nnz) receive the sparsified CSR,
+ * rows still sorted; *out_nnz (host) its entry count.  Synchronises the stream. */
+int arb_sparsify(const arb_csr *g, const int32_t *colors, int64_t *out_offsets, int32_t *out_indices,
+                 int64_t *out_nnz, void *ws, size_t ws_bytes, void *stream);
+
+/* count * colors^(k-1): the unbiased estimate of the k-clique count of the original
+ * graph from the count of the graph sparsified with that many colours. */
+double arb_colorful_estimate(uint64_t count, int colors, int k);
+
 /* Per-root features in rank space: feat[3v..3v+2] = (log2(1+d+(v)),
  * log2(1 + sum_{u in N+(v)} d+(u)), round(v)); round_orig/rank as from arb_orient. */
 int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank,

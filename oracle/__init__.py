@@ -45,7 +45,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_SO):
+    if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         build(force=True)
     lib = ctypes.CDLL(_SO)
     P = ctypes.c_void_p
@@ -66,6 +66,8 @@ def _load():
     lib.orc_local_cliques_roots.restype = None
     lib.orc_vertex_cliques.argtypes = [i64, P, P, i32, P, i64, i32, P]
     lib.orc_vertex_cliques.restype = None
+    lib.orc_sparsify.argtypes = [i64, P, P, P, P, P]
+    lib.orc_sparsify.restype = i64
     _lib = lib
     return lib
 
@@ -174,6 +176,23 @@ def vertex_cliques(g, k: int, verts, nthreads: int = 0) -> np.ndarray:
         _load().orc_vertex_cliques(g.n, _ptr(off), _ptr(idx), int(k), _ptr(verts), verts.shape[0], int(nthreads),
                                    _ptr(out))
     return out[:verts.shape[0]]
+
+
+def sparsify(g, colors):
+    """Colorful sparsification of g with the given colours: a graph object like g."""
+    off, idx = _csr(g)
+    col = np.ascontiguousarray(colors, np.int32)
+    if col.shape[0] == 0:
+        col = np.zeros(1, np.int32)
+    out_off = np.zeros(g.n + 1, np.int64)
+    out_idx = np.zeros(max(idx.shape[0], 1), np.int32)
+    nnz = _load().orc_sparsify(g.n, _ptr(off), _ptr(idx), _ptr(col), _ptr(out_off), _ptr(out_idx))
+    return type(g)(g.n, out_off, out_idx[:nnz].copy())
+
+
+def colorful_estimate(count: int, c: int, k: int) -> float:
+    """count * c^(k-1): the appendix's unbiased estimator Y = C / p^(k-1), p = 1/c."""
+    return float(count) * float(c) ** (k - 1)
 
 
 def features(n: int, ooff: np.ndarray, oidx: np.ndarray, round_rank_space: np.ndarray) -> np.ndarray:

@@ -19,6 +19,8 @@
  *   orc_local_cliques       c_j(v) = number of j-cliques inside G[N+(v)] of a directed
  *                           graph (the per-root subproblem of Alg. 1)
  *   orc_local_cliques_roots the same for a list of roots (sampled checks of large graphs)
+ *   orc_sparsify            colorful sparsification: the edges whose endpoints share a
+ *                           colour (Sec. 3.3, appendix sampling theorem)
  *   orc_vertex_cliques      the number of k-cliques containing each listed vertex of an
  *                           undirected graph, from its own neighbourhood (arb-count-v's
  *                           per-vertex count, Sec. 3.2, by definition)
@@ -517,4 +519,22 @@ void orc_vertex_cliques(int64_t n, const int64_t *off, const int32_t *idx, int k
         for (int j = 0; j <= k; j++) free(buf[j]);
         free(buf);
     }
+}
+
+/*
+ * Colorful sparsification: keep the edge {u, v} iff colors[u] == colors[v].  Rows keep
+ * their order.  out_off has n+1 entries, out_idx room for every entry of idx; returns
+ * the number of kept entries.
+ */
+int64_t orc_sparsify(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *colors, int64_t *out_off,
+                     int32_t *out_idx)
+{
+    int64_t at = 0;
+    for (int64_t v = 0; v < n; v++) {
+        out_off[v] = at;
+        for (int64_t e = off[v]; e < off[v + 1]; e++)
+            if (colors[idx[e]] == colors[v]) out_idx[at++] = idx[e];
+    }
+    out_off[n] = at;
+    return at;
 }

@@ -69,6 +69,9 @@ _sigs = {
     "arb_orient_batch_workspace": ([I64, I64, I64], SZ),
     "arb_orient_batch": ([P, P, I64, I64, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
     "arb_count_batch_workspace": ([I64, I64, I32, I64], SZ),
+    "arb_sparsify_workspace": ([I64, I64], SZ),
+    "arb_sparsify": ([P, P, P, P, P, P, SZ, P], I32),
+    "arb_colorful_estimate": ([ctypes.c_uint64, I32, I32], DBL),
     "arb_count_batch_async": ([P, P, I64, I32, P, P, P, P, P, SZ, P], I32),
     "arb_validate": ([P, P, SZ, P], I32),
     "arb_check_oriented": ([P, P, SZ, P], I32),
@@ -218,6 +221,32 @@ def arb_orient_batch(offsets: torch.Tensor, indices: torch.Tensor, graph_vtx_off
     _check(rc, "arb_orient_batch")
     return dict(ooff=ooff, oidx=oidx[: nnz // 2], rank=rank[:n], round=rnd[:n], deg_at_peel=dap[:n],
                 stats=stats, n=n, m=nnz // 2, vo=vo, G=G)
+
+
+def arb_sparsify_workspace(n: int, nnz: int) -> int:
+    return int(_lib.arb_sparsify_workspace(n, nnz))
+
+
+def arb_sparsify(offsets, indices, colors, stream=None):
+    """Colorful sparsification: (offsets, indices) of the graph that keeps the edges whose
+    endpoints share a colour (colors: device int32[n])."""
+    n = offsets.numel() - 1
+    nnz = indices.numel()
+    dev = offsets.device
+    g = ArbCsr(n, nnz, offsets.data_ptr(), indices.data_ptr() if nnz else 0)
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    out_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    out_nnz = ctypes.c_int64(0)
+    ws = _ws(_lib.arb_sparsify_workspace(n, nnz), dev)
+    _check(_lib.arb_sparsify(ctypes.byref(g), _ptr(colors), _ptr(out_off), _ptr(out_idx), ctypes.byref(out_nnz),
+                             _ptr(ws), ws.numel(), _stream(stream)), "arb_sparsify")
+    return out_off, out_idx[: out_nnz.value]
+
+
+def arb_colorful_estimate(count: int, colors: int, k: int) -> float:
+    y = float(_lib.arb_colorful_estimate(int(count), int(colors), int(k)))
+    _check(arb_last_error(), "arb_colorful_estimate")
+    return y
 
 
 def arb_validate(offsets, indices, stream=None) -> int:

@@ -417,6 +417,12 @@ def batch_mix(count: int = 256, m_lo: float = 1e4, m_hi: float = 5e5, seed_base:
     return out
 
 
+def colors(n: int, c: int, seed: int) -> np.ndarray:
+    """int32[n]: a colour per vertex, independent and uniform over 0..c-1 (the random
+    choice of colorful sparsification, drawn here and passed to both sides)."""
+    return rng(seed).integers(0, c, size=n).astype(np.int32)
+
+
 def relabel(gr: Graph, perm: np.ndarray) -> Graph:
     """Graph with vertex v renamed perm[v]."""
     u, v = gr.edges()

@@ -309,3 +309,62 @@ def test_vertex_cliques_agree_with_per_vertex_count(orc):
         for k in (3, 4, 5):
             _, pv = orc.count(g, k, per_vertex=True, nthreads=4)
             assert np.array_equal(orc.vertex_cliques(g, k, verts, nthreads=4), pv[verts]), (g.name, k)
+
+
+def _induced(g, verts):
+    """Subgraph of g induced by verts (relabelled 0..len-1), built with numpy."""
+    verts = np.sort(np.asarray(verts))
+    pos = -np.ones(g.n, np.int64)
+    pos[verts] = np.arange(verts.size)
+    u = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    v = g.indices.astype(np.int64)
+    keep = (pos[u] >= 0) & (pos[v] >= 0) & (u < v)
+    return gg.csr_from_pairs(verts.size, pos[u[keep]], pos[v[keep]])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_sparsify_keeps_the_monochromatic_cliques(orc, seed):
+    # the sparsified graph is the disjoint union of the colour classes' induced subgraphs,
+    # so its k-cliques are the monochromatic k-cliques of G
+    g = gg.gnp(300, 0.12, seed)
+    for c in (1, 2, 3, 5):
+        col = gg.colors(g.n, c, 100 + seed)
+        h = orc.sparsify(g, col)
+        assert orc.validate(h) == 0
+        for k in (2, 3, 4):
+            want = sum(orc.count(_induced(g, np.nonzero(col == x)[0]), k) for x in range(c))
+            assert orc.count(h, k) == want, (c, k)
+    assert orc.sparsify(g, np.zeros(g.n, np.int32)).m == g.m
+
+
+def _clique_pairs(g, k):
+    """All k-cliques (brute force) and s_z = ordered pairs of distinct k-cliques sharing
+    z vertices."""
+    import itertools
+    adj = [set(g.indices[g.offsets[v]:g.offsets[v + 1]].tolist()) for v in range(g.n)]
+    cl = [set(c) for c in itertools.combinations(range(g.n), k)
+          if all(b in adj[a] for a, b in itertools.combinations(c, 2))]
+    s = [0] * (k + 1)
+    for i, a in enumerate(cl):
+        for j, b in enumerate(cl):
+            if i != j:
+                s[len(a & b)] += 1
+    return len(cl), s
+
+
+def test_colorful_estimator_mean_and_variance(orc):
+    # the appendix's sampling theorem: E[Y] = X and
+    # Var[Y] = p^-2(k-1) (X (p^(k-1) - p^2(k-1)) + sum_{z=2}^{k-1} s_z (p^(2(k-1)-z+1) - p^2(k-1)))
+    g = gg.gnp(16, 0.55, 5)
+    k, c, T = 3, 2, 4000
+    p = 1.0 / c
+    X, s = _clique_pairs(g, k)
+    assert X == orc.count(g, k)
+    var = p ** (-2 * (k - 1)) * (X * (p ** (k - 1) - p ** (2 * (k - 1))) +
+                                 sum(s[z] * (p ** (2 * (k - 1) - z + 1) - p ** (2 * (k - 1))) for z in range(2, k)))
+    ys = np.array([orc.colorful_estimate(orc.count(orc.sparsify(g, gg.colors(g.n, c, 9000 + t)), k), c, k)
+                   for t in range(T)])
+    assert abs(ys.mean() - X) <= 5.0 * np.sqrt(var / T), (ys.mean(), X, var)
+    # sample variance of T draws: within 15% of the theorem's value (its own relative
+    # standard error is about sqrt(2/T) times a kurtosis factor, a few percent here)
+    assert abs(ys.var(ddof=1) / var - 1.0) < 0.15, (ys.var(ddof=1), var)
