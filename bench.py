@@ -434,6 +434,31 @@ def main():
                           "estimate": est, "rel_error": (est - tot[kx]) / tot[kx] if tot[kx] else None}
     out["colorful_sparsification"] = approx
 
+    # ---------------------------------------------------------------- orientation study
+    # the orderings the paper compares (Sec. 5): orientation time, largest out-degree and
+    # the count of the largest k on each (degree schedule, library defaults)
+    study = {}
+    for name, meth in (("peel", arb.ARB_ORIENT_PEEL), ("degree", arb.ARB_ORIENT_DEGREE),
+                       ("goodrich_pszona", arb.ARB_ORIENT_GOODRICH_PSZONA), ("kcore", arb.ARB_ORIENT_KCORE)):
+        arb.arb_orient_method(off, idx, meth, eps=a.eps)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        om = arb.arb_orient_method(off, idx, meth, eps=a.eps)
+        torch.cuda.synchronize()
+        t_or = time.time() - t1
+        wsx = arb.CountWorkspace(om["ooff"], om["oidx"], kx)
+        arb.arb_count(om["ooff"], om["oidx"], kx, ws=wsx)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        cnt = arb.arb_count(om["ooff"], om["oidx"], kx, ws=wsx)
+        t_ct = time.time() - t1
+        if cnt != tot[kx]:
+            raise SystemExit(f"ordering {name} changed the k={kx} count")
+        study[name] = {"orient_ms": t_or * 1e3, "rounds": int(om["stats"][0]), "max_outdeg": int(om["stats"][1]),
+                       f"count_k{kx}_ms": t_ct * 1e3}
+        del wsx
+    out["orientation_study"] = study
+
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, ks, a.cpu_seconds)

@@ -108,6 +108,25 @@ int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *out,
                int32_t *rank, int32_t *round, int32_t *deg_at_peel, int64_t *stats,
                void *ws, size_t ws_bytes, void *stream);
 
+/* Orderings for arb_orient_method (Sec. 3.1 and the experiments of Sec. 5):
+ *   ARB_ORIENT_PEEL  the peel of arb_orient (degree <= (2+eps) x average remaining);
+ *   ARB_ORIENT_DEGREE  by degree (ties by id): one round, round = 0, degree at removal = degree;
+ *   ARB_ORIENT_GOODRICH_PSZONA  Alg. 3: each round removes the ceil(eps c / (2 + eps))
+ *     present vertices of lowest (degree, id), c = number present (eps > 0);
+ *   ARB_ORIENT_KCORE  round r removes every present vertex of degree <= T_r,
+ *     T_r = max(T_{r-1}, least degree present) (T_{-1} = 0): a degeneracy ordering,
+ *     out-degree <= degeneracy.
+ * All rank by (round, degree at removal, id). */
+enum { ARB_ORIENT_PEEL = 0, ARB_ORIENT_DEGREE = 1, ARB_ORIENT_GOODRICH_PSZONA = 2, ARB_ORIENT_KCORE = 3 };
+
+/* arb_orient with the ordering `method`; arguments, workspace and errors as arb_orient.
+ * stats[0] = rounds (thresholds stats[2..] only for ARB_ORIENT_PEEL).  The Goodrich-
+ * Pszona and k-core orderings synchronise the stream (a host check per round / per 64
+ * rounds) and cannot be captured. */
+int arb_orient_method(const arb_csr *g, int method, double eps, int validate, arb_ocsr *out, int32_t *rank,
+                      int32_t *round_out, int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* Workspace of arb_orient_batch for a union of G graphs. */
 size_t arb_orient_batch_workspace(int64_t n, int64_t nnz, int64_t G);
 

@@ -66,6 +66,8 @@ def _load():
     lib.orc_local_cliques_roots.restype = None
     lib.orc_vertex_cliques.argtypes = [i64, P, P, i32, P, i64, i32, P]
     lib.orc_vertex_cliques.restype = None
+    lib.orc_orient_method.argtypes = [i64, P, P, i32, dbl, P, P, P, P, P, P, i32]
+    lib.orc_orient_method.restype = i32
     lib.orc_sparsify.argtypes = [i64, P, P, P, P, P]
     lib.orc_sparsify.restype = i64
     _lib = lib
@@ -91,19 +93,25 @@ def validate(g) -> int:
     return int(_load().orc_validate(g.n, _ptr(off), _ptr(idx)))
 
 
-def orient(g, eps: float = 1.0, max_rounds: int = 4096):
-    """Peel orientation.  Returns dict with round, deg_at_peel, rank (int32[n]),
+ORIENT_PEEL, ORIENT_DEGREE, ORIENT_GOODRICH_PSZONA, ORIENT_KCORE = range(4)
+
+
+def orient(g, eps: float = 1.0, max_rounds: int = 4096, method: int = ORIENT_PEEL):
+    """Orientation by the peel (method 0) or by the degree (1), Goodrich-Pszona (2) or
+    k-core (3) ordering.  Returns dict with round, deg_at_peel, rank (int32[n]),
     ooff (int64[n+1]), oidx (int32[m]) in rank space, thresholds (int64[rounds])."""
     off, idx = _csr(g)
     n = g.n
+    if method == ORIENT_KCORE:
+        max_rounds = max(max_rounds, n + 1)
     rnd = np.zeros(max(n, 1), np.int32)
     dap = np.zeros(max(n, 1), np.int32)
     rank = np.zeros(max(n, 1), np.int32)
     ooff = np.zeros(n + 1, np.int64)
     oidx = np.zeros(max(g.m, 1), np.int32)
     thr = np.zeros(max_rounds, np.int64)
-    r = _load().orc_orient(n, _ptr(off), _ptr(idx), float(eps), _ptr(rnd), _ptr(dap), _ptr(rank),
-                           _ptr(ooff), _ptr(oidx), _ptr(thr), max_rounds)
+    r = _load().orc_orient_method(n, _ptr(off), _ptr(idx), int(method), float(eps), _ptr(rnd), _ptr(dap),
+                                  _ptr(rank), _ptr(ooff), _ptr(oidx), _ptr(thr), max_rounds)
     if r < 0:
         raise RuntimeError("orientation exceeded max_rounds")
     return dict(round=rnd[:n], deg_at_peel=dap[:n], rank=rank[:n], ooff=ooff,

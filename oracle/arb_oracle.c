@@ -11,6 +11,8 @@
  *   orc_orient              Barenboim-Elkin style peel with the average-degree threshold
  *                           (Sec. 3.1 and Alg. 4 of the appendix), ranks, directed CSR
  *                           (Sec. 3.1, last paragraph)
+ *   orc_orient_method       the same with the degree, Goodrich-Pszona (Alg. 3) or k-core
+ *                           ordering
  *   orc_count               Chiba-Nishizeki recursion with level labels (Sec. 3.4; the
  *                           count is the plain definition: every k-vertex subset whose
  *                           pairs are all adjacent, counted once from its first vertex)
@@ -105,9 +107,27 @@ static int cmp_i32(const void *a, const void *b)
  * thr_out (nullable, max_rounds entries) receives T per round.  Returns the number of
  * rounds, or -1 if max_rounds is exceeded.
  */
-int orc_orient(int64_t n, const int64_t *off, const int32_t *idx, double eps,
-               int32_t *round_out, int32_t *dap_out, int32_t *rank_out,
-               int64_t *ooff_out, int32_t *oidx_out, int64_t *thr_out, int max_rounds)
+/* present vertices sorted by (degree, id) (Goodrich-Pszona rounds) */
+static const int32_t *g_deg_key;
+static int cmp_deg_id(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    if (g_deg_key[x] != g_deg_key[y]) return g_deg_key[x] < g_deg_key[y] ? -1 : 1;
+    return x < y ? -1 : (x > y);
+}
+
+/*
+ * The same with another rule for the vertices removed in round r (method):
+ *   0  degree <= floor(((2 + eps) * S) / c), as above;
+ *   1  degree ordering: every vertex in round 0 (the rank is by degree, then id);
+ *   2  Goodrich-Pszona (Alg. 3): the ceil((eps * c) / (2 + eps)) present vertices of
+ *      lowest (degree, id), at least one;
+ *   3  k-core ordering: degree <= T_r, T_r = max(T_{r-1}, least present degree), T_{-1} = 0.
+ * thr_out receives T per round for methods 0 and 3.
+ */
+int orc_orient_method(int64_t n, const int64_t *off, const int32_t *idx, int method, double eps,
+                      int32_t *round_out, int32_t *dap_out, int32_t *rank_out,
+                      int64_t *ooff_out, int32_t *oidx_out, int64_t *thr_out, int max_rounds)
 {
     int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (n + 1));
     uint8_t *present = (uint8_t *)malloc(n + 1);
@@ -115,24 +135,50 @@ int orc_orient(int64_t n, const int64_t *off, const int32_t *idx, double eps,
     int32_t *inv = (int32_t *)malloc(sizeof(int32_t) * (n + 1));
     int64_t left = n;
     int r = 0;
+    int64_t Tk = 0;                     /* k-core: running threshold */
     for (int64_t v = 0; v < n; v++) {
         deg[v] = (int32_t)(off[v + 1] - off[v]);
         present[v] = 1;
     }
     while (left > 0) {
         if (r >= max_rounds) { r = -1; goto done; }
-        int64_t S = 0, c = 0;
+        int64_t S = 0, c = 0, mn = INT64_MAX;
         for (int64_t v = 0; v < n; v++)
-            if (present[v]) { S += deg[v]; c++; }
-        double t = ((2.0 + eps) * (double)S) / (double)c;
-        int64_t T = (int64_t)floor(t);
-        if (thr_out) thr_out[r] = T;
+            if (present[v]) { S += deg[v]; c++; if (deg[v] < mn) mn = deg[v]; }
         int64_t np = 0;
-        for (int64_t v = 0; v < n; v++) {
-            if (present[v] && (int64_t)deg[v] <= T) {
-                peeled[np++] = (int32_t)v;
+        if (method == 2) {
+            /* the s present vertices of lowest (degree, id) */
+            int64_t sr = (int64_t)ceil((eps * (double)c) / (2.0 + eps));
+            if (sr < 1) sr = 1;
+            if (sr > c) sr = c;
+            int64_t q = 0;
+            for (int64_t v = 0; v < n; v++) if (present[v]) inv[q++] = (int32_t)v;
+            g_deg_key = deg;
+            qsort(inv, (size_t)c, sizeof(int32_t), cmp_deg_id);
+            for (int64_t i = 0; i < sr; i++) {
+                int32_t v = inv[i];
+                peeled[np++] = v;
                 round_out[v] = r;
                 dap_out[v] = deg[v];
+            }
+        } else {
+            int64_t T;
+            if (method == 0) {
+                double t = ((2.0 + eps) * (double)S) / (double)c;
+                T = (int64_t)floor(t);
+            } else if (method == 1) {
+                T = INT64_MAX;
+            } else {
+                if (mn > Tk) Tk = mn;
+                T = Tk;
+            }
+            if (thr_out && method != 1) thr_out[r] = T;
+            for (int64_t v = 0; v < n; v++) {
+                if (present[v] && (int64_t)deg[v] <= T) {
+                    peeled[np++] = (int32_t)v;
+                    round_out[v] = r;
+                    dap_out[v] = deg[v];
+                }
             }
         }
         for (int64_t i = 0; i < np; i++) present[peeled[i]] = 0;
@@ -168,6 +214,14 @@ int orc_orient(int64_t n, const int64_t *off, const int32_t *idx, double eps,
 done:
     free(deg); free(present); free(peeled); free(inv);
     return r;
+}
+
+int orc_orient(int64_t n, const int64_t *off, const int32_t *idx, double eps,
+               int32_t *round_out, int32_t *dap_out, int32_t *rank_out,
+               int64_t *ooff_out, int32_t *oidx_out, int64_t *thr_out, int max_rounds)
+{
+    return orc_orient_method(n, off, idx, 0, eps, round_out, dap_out, rank_out, ooff_out, oidx_out, thr_out,
+                             max_rounds);
 }
 
 /* ------------------------------------------------------------------ CN counting */

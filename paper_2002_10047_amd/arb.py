@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 ARB_OK, ARB_EINVAL, ARB_EGRAPH, ARB_EWORKSPACE, ARB_EHIP, ARB_ELIMIT, ARB_EMISMATCH = range(7)
 ARB_SCHED_PLAIN, ARB_SCHED_PERSISTENT, ARB_SCHED_LEARNED = range(3)
+ARB_ORIENT_PEEL, ARB_ORIENT_DEGREE, ARB_ORIENT_GOODRICH_PSZONA, ARB_ORIENT_KCORE = range(4)
 
 
 def _define(name):
@@ -66,6 +67,7 @@ P, I64, I32, SZ, DBL, FLT = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctyp
 _sigs = {
     "arb_orient_workspace": ([I64, I64], SZ),
     "arb_orient": ([P, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
+    "arb_orient_method": ([P, I32, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
     "arb_orient_batch_workspace": ([I64, I64, I64], SZ),
     "arb_orient_batch": ([P, P, I64, I64, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
     "arb_count_batch_workspace": ([I64, I64, I32, I64], SZ),
@@ -179,6 +181,28 @@ def arb_orient(offsets: torch.Tensor, indices: torch.Tensor, eps: float = 1.0, v
     rc = _lib.arb_orient(ctypes.byref(g), float(eps), int(bool(validate)), ctypes.byref(out), _ptr(rank),
                          _ptr(rnd), _ptr(dap), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "arb_orient")
+    return dict(ooff=ooff, oidx=oidx[: nnz // 2], rank=rank[:n], round=rnd[:n], deg_at_peel=dap[:n],
+                stats=stats, n=n, m=nnz // 2)
+
+
+def arb_orient_method(offsets: torch.Tensor, indices: torch.Tensor, method: int, eps: float = 1.0,
+                      validate: bool = False, stream=None):
+    """arb_orient_method (ARB_ORIENT_*): the same dict as arb_orient."""
+    n = offsets.numel() - 1
+    nnz = indices.numel()
+    dev = offsets.device
+    g = ArbCsr(n, nnz, offsets.data_ptr(), indices.data_ptr() if nnz else 0)
+    ooff = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    oidx = torch.empty(max(nnz // 2, 1), dtype=torch.int32, device=dev)
+    out = ArbOcsr(n, nnz // 2, ooff.data_ptr(), oidx.data_ptr())
+    rank = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rnd = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    dap = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    stats = torch.empty(2 + ARB_MAX_ROUNDS, dtype=torch.int64, device=dev)
+    ws = _ws(_lib.arb_orient_workspace(n, nnz), dev)
+    rc = _lib.arb_orient_method(ctypes.byref(g), int(method), float(eps), int(bool(validate)), ctypes.byref(out),
+                                _ptr(rank), _ptr(rnd), _ptr(dap), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "arb_orient_method")
     return dict(ooff=ooff, oidx=oidx[: nnz // 2], rank=rank[:n], round=rnd[:n], deg_at_peel=dap[:n],
                 stats=stats, n=n, m=nnz // 2)
 

@@ -127,9 +127,10 @@ __global__ void k_peel_mark(int64_t n, const int32_t *deg, int32_t *rnd, int32_t
 
 // Each wave looks at 64 consecutive vertices; for every one removed in round r (ballot),
 // the whole wave walks its row and decrements neighbours still present.
+// act[0] < 0: nothing was present at the start of round r (the round is a no-op)
 __global__ void k_peel_decrement(int64_t n, const int64_t *off, const int32_t *idx, int32_t *deg,
-                                 const int32_t *rnd, int r, const int64_t *thr) {
-    if (thr[r] < 0) return;
+                                 const int32_t *rnd, int r, const int64_t *act) {
+    if (act[0] < 0) return;
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -270,12 +271,103 @@ __global__ void k_gid_keys(int64_t n, const int32_t *vals, const int32_t *gid, u
         keys[p] = (uint32_t)gid[vals[p]];
 }
 
+// ------------------------------------------------------------------ other orderings
+// (the orientations the paper compares, Sec. 3.1, 5: degree ordering, Goodrich-Pszona
+// (Alg. 3), k-core ordering); all end in the same (round, degree at removal, id) ranking
+
+// degree ordering: every vertex in round 0 with its degree, so the rank orders by (degree, id)
+__global__ void k_all_round0(int64_t n, const int32_t *deg, int32_t *rnd, int32_t *dap) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        rnd[v] = 0;
+        dap[v] = deg[v];
+    }
+}
+
+__global__ void k_present_flags(int64_t n, const int32_t *rnd, int64_t *flag) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = rnd[v] == kPresent ? 1 : 0;
+}
+
+// present vertices in id order: keys = degree, vals = id
+__global__ void k_present_compact(int64_t n, const int32_t *rnd, const int32_t *deg, const int64_t *pos,
+                                  uint32_t *keys, int32_t *vals) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (rnd[v] == kPresent) {
+            keys[pos[v]] = (uint32_t)deg[v];
+            vals[pos[v]] = (int32_t)v;
+        }
+}
+
+// Goodrich-Pszona round r: the s present vertices of lowest (degree, id) are removed
+__global__ void k_gp_mark(int64_t s, const int32_t *vals, const int32_t *deg, int32_t *rnd, int32_t *dap, int r) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = vals[i];
+        rnd[v] = r;
+        dap[v] = deg[v];
+    }
+}
+
+// k-core round: st[0] = least degree present, st[1] = number present (st reset by the
+// threshold kernel)
+__global__ void k_kcore_reduce(int64_t n, const int32_t *deg, const int32_t *rnd, int64_t *st) {
+    int64_t c = 0, mn = INT64_MAX;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (rnd[v] == kPresent) {
+            c += 1;
+            mn = deg[v] < mn ? deg[v] : mn;
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        const int64_t y = __shfl_xor(mn, o, 64);
+        mn = y < mn ? y : mn;
+    }
+    if ((threadIdx.x & 63) == 0 && c) {
+        atomicAdd((unsigned long long *)&st[1], (unsigned long long)c);
+        atomicMin((long long *)&st[0], (long long)mn);
+    }
+}
+
+// T[0] = max(T[0], least degree present), or -1 once nothing is present; st[2] counts
+// the rounds that peeled
+__global__ void k_kcore_threshold(int64_t *st, int64_t *T) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (st[1] == 0) {
+        T[0] = -1;
+    } else {
+        T[0] = st[0] > T[0] ? st[0] : T[0];
+        st[2] += 1;
+    }
+    st[0] = INT64_MAX;
+    st[1] = 0;
+}
+
+__global__ void k_kcore_mark(int64_t n, const int32_t *deg, int32_t *rnd, int32_t *dap, int r, const int64_t *T) {
+    const int64_t t = T[0];
+    if (t < 0) return;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (rnd[v] == kPresent && (int64_t)deg[v] <= t) {
+            rnd[v] = r;
+            dap[v] = deg[v];
+        }
+}
+
+// second rank key when rounds do not fit beside the degree: the round of each position
+__global__ void k_round_keys(int64_t n, const int32_t *vals, const int32_t *rnd, uint32_t *keys) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        keys[p] = (uint32_t)rnd[vals[p]];
+}
+
+__global__ void k_set_stat(int64_t *stats, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) stats[0] = v;
+}
+
 // ------------------------------------------------------------------ rank
 
 __global__ void k_rank_keys(int64_t n, const int32_t *rnd, const int32_t *dap, uint32_t *keys, int32_t *vals) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        keys[v] = ((uint32_t)rnd[v] << kDegBits) | (uint32_t)dap[v];
+        keys[v] = ((rnd ? (uint32_t)rnd[v] : 0u) << kDegBits) | (uint32_t)dap[v];
         vals[v] = (int32_t)v;
     }
 }
@@ -506,9 +598,11 @@ struct BatchDesc {
 
 static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out, int32_t *rank,
                        int32_t *round_out, int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes,
-                       hipStream_t s, const BatchDesc *b) {
+                       hipStream_t s, const BatchDesc *b, int method = ARB_ORIENT_PEEL) {
     if (!g || !out || !rank || !ws) return ARB_EINVAL;
     if (!(eps >= 0.0 && eps <= 64.0)) return ARB_EINVAL;
+    if (method < ARB_ORIENT_PEEL || method > ARB_ORIENT_KCORE || (b && method != ARB_ORIENT_PEEL)) return ARB_EINVAL;
+    if (method == ARB_ORIENT_GOODRICH_PSZONA && !(eps > 0.0)) return ARB_EINVAL;
     const int64_t n = g->n, nnz = g->nnz;
     if (n < 0 || nnz < 0 || (nnz & 1)) return ARB_EINVAL;
     if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) return ARB_ELIMIT;
@@ -555,32 +649,97 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
     }
     k_orient_init<<<gb, 256, 0, s>>>(n, g->offsets, w.deg, rnd, w.err);
     if (hipGetLastError() != hipSuccess) return ARB_EHIP;
-    const int R = max_rounds(b ? b->max_n : n, eps);
-    if (R > 120) return ARB_ELIMIT;
-    for (int r = 0; r < R; ++r) {
-        if (b) {
-            if ((rc = fill_i64(w.rs_g, 0, 2 * G, s))) return rc;
-            k_bpeel_reduce<<<gw, 256, 0, s>>>(n, w.deg, rnd, w.gid, w.rs_g);
-            k_bpeel_threshold<<<grid_for(G, 256, 1024), 256, 0, s>>>(G, r, eps, w.rs_g, w.thr_g, w.thr, stats);
-            k_bpeel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, w.gid, r, w.thr_g, w.thr);
-        } else {
-            k_peel_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, r, w.rs);
-            k_peel_threshold<<<1, 64, 0, s>>>(r, eps, w.rs, w.thr, stats);
-            k_peel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, w.thr);
+    int64_t R = 0;                                  // rounds the rank key must hold
+    if (method == ARB_ORIENT_PEEL) {
+        R = max_rounds(b ? b->max_n : n, eps);
+        if (R > 120) return ARB_ELIMIT;
+        for (int r = 0; r < R; ++r) {
+            if (b) {
+                if ((rc = fill_i64(w.rs_g, 0, 2 * G, s))) return rc;
+                k_bpeel_reduce<<<gw, 256, 0, s>>>(n, w.deg, rnd, w.gid, w.rs_g);
+                k_bpeel_threshold<<<grid_for(G, 256, 1024), 256, 0, s>>>(G, r, eps, w.rs_g, w.thr_g, w.thr, stats);
+                k_bpeel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, w.gid, r, w.thr_g, w.thr);
+            } else {
+                k_peel_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, r, w.rs);
+                k_peel_threshold<<<1, 64, 0, s>>>(r, eps, w.rs, w.thr, stats);
+                k_peel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, w.thr);
+            }
+            k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, w.thr + r);
         }
-        k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, w.thr);
+    } else if (method == ARB_ORIENT_DEGREE) {
+        k_all_round0<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap);
+        R = 1;
+        if (stats) k_set_stat<<<1, 64, 0, s>>>(stats, n > 0 ? 1 : 0);
+    } else if (method == ARB_ORIENT_GOODRICH_PSZONA) {
+        // Alg. 3: each round removes the ceil(eps c / (2 + eps)) present vertices of lowest
+        // (degree, id), c = number present (host loop: one synchronisation per round)
+        int64_t *act = w.rs;                         // >= 0: the decrement runs
+        if ((rc = fill_i64(act, 0, 1, s))) return rc;
+        int r = 0;
+        while (true) {
+            k_present_flags<<<gb, 256, 0, s>>>(n, rnd, w.outdeg);
+            if ((rc = exclusive_scan_i64(w.outdeg, w.outdeg, n, w.scan_ws, s))) return rc;
+            int64_t c = 0;
+            ARB_HIP(hipMemcpyAsync(&c, w.outdeg + n, sizeof(c), hipMemcpyDeviceToHost, s));
+            ARB_HIP(hipStreamSynchronize(s));
+            if (c == 0) break;
+            if (r >= (1 << 20)) return ARB_ELIMIT;
+            int64_t sr = (int64_t)ceil((eps * (double)c) / (2.0 + eps));
+            if (sr < 1) sr = 1;
+            if (sr > c) sr = c;
+            k_present_compact<<<gb, 256, 0, s>>>(n, rnd, w.deg, w.outdeg, w.keys, w.vals);
+            if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, c, kDegBits, w.radix_ws, s))) return rc;
+            k_gp_mark<<<grid_for(sr, 256, 4096), 256, 0, s>>>(sr, w.vals, w.deg, rnd, dap, r);
+            k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, act);
+            ++r;
+        }
+        R = r;
+        if (stats) k_set_stat<<<1, 64, 0, s>>>(stats, r);
+    } else {
+        // k-core ordering: round r removes every present vertex of degree <= T_r,
+        // T_r = max(T_{r-1}, least degree present); launched 64 rounds at a time
+        int64_t *st = w.rs, *T = w.rs + 4;
+        if ((rc = fill_i64(st, INT64_MAX, 1, s)) || (rc = fill_i64(st + 1, 0, 2, s)) || (rc = fill_i64(T, 0, 1, s)))
+            return rc;
+        int r = 0;
+        while (true) {
+            for (int i = 0; i < 64; ++i, ++r) {
+                k_kcore_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, st);
+                k_kcore_threshold<<<1, 64, 0, s>>>(st, T);
+                k_kcore_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, T);
+                k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, T);
+            }
+            int64_t h[2] = {0, 0};
+            ARB_HIP(hipMemcpyAsync(&h[0], T, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            ARB_HIP(hipMemcpyAsync(&h[1], st + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            ARB_HIP(hipStreamSynchronize(s));
+            if (h[0] < 0) {
+                R = h[1];
+                break;
+            }
+            if (r > n + 64) return ARB_ELIMIT;       // every round with a vertex present removes one
+        }
+        if (stats) k_set_stat<<<1, 64, 0, s>>>(stats, R);
     }
     k_count_left<<<gb, 256, 0, s>>>(n, rnd, w.err);
     if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     // rank: stable sort of ids by (round, degree at removal); in a batch then stably by
     // graph, which keeps every graph's ranks inside its own vertex range
-    k_rank_keys<<<gb, 256, 0, s>>>(n, rnd, dap, w.keys, w.vals);
-    if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     int round_bits = 1;
-    while ((1 << round_bits) <= R) ++round_bits;
-    if (kDegBits + round_bits > 32) return ARB_ELIMIT;
-    if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, kDegBits + round_bits, w.radix_ws, s)))
-        return rc;
+    while ((int64_t(1) << round_bits) <= R) ++round_bits;
+    if (kDegBits + round_bits <= 32) {
+        k_rank_keys<<<gb, 256, 0, s>>>(n, rnd, dap, w.keys, w.vals);
+        if (hipGetLastError() != hipSuccess) return ARB_EHIP;
+        if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, kDegBits + round_bits, w.radix_ws, s)))
+            return rc;
+    } else {
+        // many rounds: by degree at removal first, then stably by round
+        k_rank_keys<<<gb, 256, 0, s>>>(n, nullptr, dap, w.keys, w.vals);
+        if (hipGetLastError() != hipSuccess) return ARB_EHIP;
+        if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, kDegBits, w.radix_ws, s))) return rc;
+        k_round_keys<<<gb, 256, 0, s>>>(n, w.vals, rnd, w.keys);
+        if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, round_bits, w.radix_ws, s))) return rc;
+    }
     if (b && G > 1) {
         k_gid_keys<<<gb, 256, 0, s>>>(n, w.vals, w.gid, w.keys);
         if (hipGetLastError() != hipSuccess) return ARB_EHIP;
@@ -626,6 +785,15 @@ extern "C" int arb_orient(const arb_csr *g, double eps, int validate, arb_ocsr *
                           void *stream) {
     const int rc = orient_impl(g, eps, validate, out, rank, round_out, dap_out, stats, ws, ws_bytes,
                                as_stream(stream), nullptr);
+    set_error(rc);
+    return rc;
+}
+
+extern "C" int arb_orient_method(const arb_csr *g, int method, double eps, int validate, arb_ocsr *out, int32_t *rank,
+                                 int32_t *round_out, int32_t *dap_out, int64_t *stats, void *ws, size_t ws_bytes,
+                                 void *stream) {
+    const int rc = orient_impl(g, eps, validate, out, rank, round_out, dap_out, stats, ws, ws_bytes,
+                               as_stream(stream), nullptr, method);
     set_error(rc);
     return rc;
 }

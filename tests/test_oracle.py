@@ -368,3 +368,48 @@ def test_colorful_estimator_mean_and_variance(orc):
     # sample variance of T draws: within 15% of the theorem's value (its own relative
     # standard error is about sqrt(2/T) times a kurtosis factor, a few percent here)
     assert abs(ys.var(ddof=1) / var - 1.0) < 0.15, (ys.var(ddof=1), var)
+
+
+def test_orderings_hand_examples(orc):
+    # path 0-1-2-3-4, Goodrich-Pszona with eps = 1 (worked by hand from Alg. 3):
+    # round 0: c = 5, ceil(5/3) = 2 lowest (degree, id) -> 0, 4; round 1: c = 3, one
+    # vertex -> 1 (degree 1); round 2: c = 2 -> 2 (degree 1, id 2 < 3); round 3 -> 3
+    p = gg.csr_from_pairs(5, np.array([0, 1, 2, 3]), np.array([1, 2, 3, 4]))
+    r = orc.orient(p, 1.0, method=orc.ORIENT_GOODRICH_PSZONA)
+    assert r["round"].tolist() == [0, 1, 2, 3, 0]
+    assert r["rank"].tolist() == [0, 2, 3, 4, 1]
+    # degree ordering of a star: leaves (degree 1) first by id, the centre last
+    s = gg.star(6)
+    d = orc.orient(s, 1.0, method=orc.ORIENT_DEGREE)
+    deg = np.diff(s.offsets)
+    centre = int(np.argmax(deg))
+    assert d["rank"][centre] == s.n - 1
+    assert np.diff(d["ooff"])[s.n - 1] == 0 and np.all(np.diff(d["ooff"])[: s.n - 1] == 1)
+    # k-core ordering of the path: thresholds 1, 1, ... (every round removes degree <= 1)
+    k = orc.orient(p, 1.0, method=orc.ORIENT_KCORE)
+    assert k["round"].tolist() == [0, 1, 2, 1, 0] and k["thresholds"].tolist() == [1, 1, 1]
+
+
+@pytest.mark.parametrize("method", [1, 2, 3])
+def test_orderings_bounds_and_invariance(orc, method):
+    import math
+    eps = 1.0
+    for g in [gg.gnp(300, 0.1, 2), gg.config_graph("c1"), gg.rmat(12, 40000, seed=3), gg.turan(40, 5),
+              gg.complete(15), gg.cycle(9)]:
+        r = orc.orient(g, eps, method=method)
+        dplus = np.diff(r["ooff"])
+        dg = orc.degeneracy(g)
+        if method == orc.ORIENT_KCORE:
+            assert dplus.max(initial=0) <= dg            # a degeneracy ordering
+        if method == orc.ORIENT_GOODRICH_PSZONA:
+            # c shrinks by a factor <= 2/(2+eps) per round; removed degrees < (2+eps) alpha
+            assert r["rounds"] <= math.ceil(math.log(max(g.n, 1)) / math.log((2 + eps) / 2)) + 1
+            assert dplus.max(initial=0) <= (2 + eps) * dg
+        if method == orc.ORIENT_DEGREE:
+            deg = np.diff(g.offsets)
+            order = np.lexsort((np.arange(g.n), deg))
+            assert np.array_equal(r["rank"][order], np.arange(g.n))
+        # every ordering counts the same cliques
+        lc = orc.local_cliques(g.n, r["ooff"], r["oidx"], 5)
+        for k in range(2, 7):
+            assert int(lc[:, k - 2].sum()) == orc.count(g, k), (g.name, method, k)
