@@ -459,6 +459,13 @@ def main():
         del wsx
     out["orientation_study"] = study
 
+    # ---------------------------------------------------------------- approximate peeling
+    # arb-approx-peel (Sec. 4.2) for k = 3 on the same graph
+    torch.cuda.synchronize()
+    t1 = time.time()
+    dens, rounds, _ = arb.arb_approx_peel(o["ooff"], o["oidx"], 3, 1.0)
+    out["approx_peel"] = {"k": 3, "eps": 1.0, "seconds": time.time() - t1, "rounds": rounds, "density": dens}
+
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, ks, a.cpu_seconds)

@@ -289,6 +289,20 @@ int arb_sparsify(const arb_csr *g, const int32_t *colors, int64_t *out_offsets, 
  * graph from the count of the graph sparsified with that many colours. */
 double arb_colorful_estimate(uint64_t count, int colors, int k);
 
+/* Workspace of arb_approx_peel. */
+size_t arb_approx_peel_workspace(int64_t n, int64_t m, int k);
+
+/* arb-approx-peel (Sec. 4.2): a 1/(k(1+eps))-approximation of the k-clique densest
+ * subgraph of the graph oriented as dg (rank space).  Rounds on the present set S (all
+ * vertices at first): count per-vertex k-cliques of G[S] (dg restricted to S), density
+ * d(S) = cliques(S) / |S|, then remove every present vertex whose count c satisfies
+ * (double)c <= ((double)k * (1 + eps) * (double)cliques(S)) / (double)|S|.
+ * *best_density = the largest d(S) met, *rounds (nullable) the rounds, best_mask
+ * (nullable, device int32[n], rank space) 1 on the S that gave it.  eps in (0, 64],
+ * 1 <= k <= ARB_MAX_K; opts as arb_count_async.  Synchronises every round. */
+int arb_approx_peel(const arb_ocsr *dg, int k, double eps, const arb_count_opts *opts, double *best_density,
+                    int64_t *rounds, int32_t *best_mask, void *ws, size_t ws_bytes, void *stream);
+
 /* Per-root features in rank space: feat[3v..3v+2] = (log2(1+d+(v)),
  * log2(1 + sum_{u in N+(v)} d+(u)), round(v)); round_orig/rank as from arb_orient. */
 int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank,

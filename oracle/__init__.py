@@ -14,6 +14,7 @@ Functions follow the paper (Shi, Dhulipala, Shun, arXiv 2002.10047):
   local_cliques   c_j(v), the j-cliques of G[N+(v)] (the per-root work of Alg. 1)
   local_cliques_roots  the same for listed roots (sampled checks at full size)
   vertex_cliques  k-cliques containing listed vertices, from each one's neighbourhood
+  approx_peel     arb-approx-peel (Sec. 4.2), rounds of per-vertex counts on the present set
   features        the per-root scheduling features (d+, sum of d+ over N+, round)
 """
 from __future__ import annotations
@@ -201,6 +202,40 @@ def sparsify(g, colors):
 def colorful_estimate(count: int, c: int, k: int) -> float:
     """count * c^(k-1): the appendix's unbiased estimator Y = C / p^(k-1), p = 1/c."""
     return float(count) * float(c) ** (k - 1)
+
+
+def _induced(g, keep):
+    """Subgraph of g on the vertices with keep[v] (same ids; the others isolated)."""
+    off, idx = _csr(g)
+    u = np.repeat(np.arange(g.n), np.diff(off))
+    v = idx[: off[-1]].astype(np.int64)
+    sel = keep[u] & keep[v]
+    deg = np.bincount(u[sel], minlength=g.n)
+    noff = np.zeros(g.n + 1, np.int64)
+    noff[1:] = np.cumsum(deg)
+    return type(g)(g.n, noff, idx[: off[-1]][sel].astype(np.int32).copy())
+
+
+def approx_peel(g, k: int, eps: float):
+    """arb-approx-peel (Sec. 4.2): while vertices remain, count the k-cliques of the
+    present set S per vertex, note the density cliques(S)/|S|, and remove every present
+    vertex with at most k(1+eps) times that density k-cliques (compared in double as
+    (double)c <= ((double)k * (1 + eps) * (double)cliques) / (double)|S|).  Returns
+    (best density, rounds, bool mask of the best S)."""
+    keep = np.ones(g.n, bool)
+    best, best_mask, rounds = -1.0, keep.copy(), 0
+    present = g.n
+    while present > 0:
+        h = _induced(g, keep)
+        C, pv = count(h, k, per_vertex=True, nthreads=8)
+        density = float(C) / float(present)
+        if density > best:
+            best, best_mask = density, keep.copy()
+        t = (float(k) * (1.0 + eps) * float(C)) / float(present)
+        keep = keep & ~(pv.astype(np.float64) <= t)
+        present = int(keep.sum())
+        rounds += 1
+    return max(best, 0.0), rounds, best_mask
 
 
 def features(n: int, ooff: np.ndarray, oidx: np.ndarray, round_rank_space: np.ndarray) -> np.ndarray:

@@ -72,6 +72,8 @@ _sigs = {
     "arb_orient_batch": ([P, P, I64, I64, DBL, I32, P, P, P, P, P, P, SZ, P], I32),
     "arb_count_batch_workspace": ([I64, I64, I32, I64], SZ),
     "arb_sparsify_workspace": ([I64, I64], SZ),
+    "arb_approx_peel_workspace": ([I64, I64, I32], SZ),
+    "arb_approx_peel": ([P, I32, DBL, P, P, P, P, P, SZ, P], I32),
     "arb_sparsify": ([P, P, P, P, P, P, SZ, P], I32),
     "arb_colorful_estimate": ([ctypes.c_uint64, I32, I32], DBL),
     "arb_count_batch_async": ([P, P, I64, I32, P, P, P, P, P, SZ, P], I32),
@@ -265,6 +267,24 @@ def arb_sparsify(offsets, indices, colors, stream=None):
     _check(_lib.arb_sparsify(ctypes.byref(g), _ptr(colors), _ptr(out_off), _ptr(out_idx), ctypes.byref(out_nnz),
                              _ptr(ws), ws.numel(), _stream(stream)), "arb_sparsify")
     return out_off, out_idx[: out_nnz.value]
+
+
+def arb_approx_peel_workspace(n: int, m: int, k: int) -> int:
+    return int(_lib.arb_approx_peel_workspace(n, m, int(k)))
+
+
+def arb_approx_peel(ooff, oidx, k, eps=1.0, opts=None, stream=None):
+    """arb-approx-peel: (best density, rounds, best mask int32[n] in rank space)."""
+    dg = _ocsr(ooff, oidx)
+    n = dg.n
+    mask = torch.empty(max(n, 1), dtype=torch.int32, device=ooff.device)
+    ws = _ws(_lib.arb_approx_peel_workspace(n, dg.m, int(k)), ooff.device)
+    dens = ctypes.c_double(0.0)
+    rounds = ctypes.c_int64(0)
+    _check(_lib.arb_approx_peel(ctypes.byref(dg), int(k), float(eps), ctypes.byref(opts) if opts is not None else None,
+                                ctypes.byref(dens), ctypes.byref(rounds), _ptr(mask), _ptr(ws), ws.numel(),
+                                _stream(stream)), "arb_approx_peel")
+    return dens.value, rounds.value, mask[:n]
 
 
 def arb_colorful_estimate(count: int, colors: int, k: int) -> float:

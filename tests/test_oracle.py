@@ -413,3 +413,35 @@ def test_orderings_bounds_and_invariance(orc, method):
         lc = orc.local_cliques(g.n, r["ooff"], r["oidx"], 5)
         for k in range(2, 7):
             assert int(lc[:, k - 2].sum()) == orc.count(g, k), (g.name, method, k)
+
+
+def _densest_brute(g, k):
+    """max over nonempty vertex subsets S of (k-cliques inside S) / |S|, n <= 14."""
+    import itertools
+    adj = [set(g.indices[g.offsets[v]:g.offsets[v + 1]].tolist()) for v in range(g.n)]
+    cl = [c for c in itertools.combinations(range(g.n), k)
+          if all(b in adj[a] for a, b in itertools.combinations(c, 2))]
+    best = 0.0
+    for mask in range(1, 1 << g.n):
+        size = bin(mask).count("1")
+        inside = sum(1 for c in cl if all(mask >> v & 1 for v in c))
+        best = max(best, inside / size)
+    return best
+
+
+def test_approx_peel_closed_form_and_guarantee(orc):
+    # K_n: every vertex has C(n-1,k-1) = k * density cliques, so one round removes all
+    for n, k in ((10, 3), (9, 4), (7, 2)):
+        d, r, mask = orc.approx_peel(gg.complete(n), k, 0.5)
+        assert d == math.comb(n, k) / n and r == 1 and mask.all()
+    # the 1/(k(1+eps)) guarantee against the exact k-clique densest subgraph (brute force)
+    for seed in (1, 2, 3):
+        g = gg.gnp(13, 0.45, seed)
+        for k, eps in ((2, 0.5), (3, 0.25), (3, 1.0), (4, 0.5)):
+            opt = _densest_brute(g, k)
+            d, r, mask = orc.approx_peel(g, k, eps)
+            assert opt / (k * (1 + eps)) - 1e-12 <= d <= opt + 1e-12, (seed, k, eps, d, opt)
+            # the reported set has that density
+            if mask.any():
+                h = orc._induced(g, mask)
+                assert orc.count(h, k) / mask.sum() == d
