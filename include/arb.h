@@ -303,6 +303,20 @@ size_t arb_approx_peel_workspace(int64_t n, int64_t m, int k);
 int arb_approx_peel(const arb_ocsr *dg, int k, double eps, const arb_count_opts *opts, double *best_density,
                     int64_t *rounds, int32_t *best_mask, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace of arb_peel. */
+size_t arb_peel_workspace(int64_t n, int64_t m, int k);
+
+/* arb-peel (Alg. 2, Sec. 4.1): k-clique vertex peeling of the graph oriented as dg, a
+ * 1/k-approximation of the k-clique densest subgraph.  From the per-vertex k-clique
+ * counts, round r removes every present vertex whose count is the least present count
+ * (round_out[v] = r, device int32[n], rank space) and lowers the others' counts by the
+ * k-cliques removed with them (counted around each removed vertex on its present
+ * neighbourhood).  *best_density = max over the vertex sets met (the whole graph first,
+ * then after every round while vertices remain) of cliques(S) / |S| (double);
+ * *rounds (nullable) = rounds.  3 <= k <= ARB_MAX_K.  Synchronises every round. */
+int arb_peel(const arb_ocsr *dg, int k, double *best_density, int64_t *rounds, int32_t *round_out, void *ws,
+             size_t ws_bytes, void *stream);
+
 /* Per-root features in rank space: feat[3v..3v+2] = (log2(1+d+(v)),
  * log2(1 + sum_{u in N+(v)} d+(u)), round(v)); round_orig/rank as from arb_orient. */
 int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank,

@@ -15,6 +15,7 @@ Functions follow the paper (Shi, Dhulipala, Shun, arXiv 2002.10047):
   local_cliques_roots  the same for listed roots (sampled checks at full size)
   vertex_cliques  k-cliques containing listed vertices, from each one's neighbourhood
   approx_peel     arb-approx-peel (Sec. 4.2), rounds of per-vertex counts on the present set
+  peel            arb-peel (Alg. 2): remove the least-count vertices, recount, repeat
   features        the per-root scheduling features (d+, sum of d+ over N+, round)
 """
 from __future__ import annotations
@@ -236,6 +237,30 @@ def approx_peel(g, k: int, eps: float):
         present = int(keep.sum())
         rounds += 1
     return max(best, 0.0), rounds, best_mask
+
+
+def peel(g, k: int):
+    """arb-peel (Alg. 2) by definition: while vertices remain, count the k-cliques of the
+    present set S per vertex (from scratch), remove every vertex with the least count
+    (its round is r), and note the density cliques / |S| of what remains (the whole
+    graph first).  Returns (best density, rounds, round per vertex)."""
+    keep = np.ones(g.n, bool)
+    rnd = -np.ones(g.n, np.int32)
+    T = count(g, k, nthreads=8)
+    best = float(T) / float(g.n) if g.n else 0.0
+    r = 0
+    while keep.any():
+        h = _induced(g, keep)
+        _, pv = count(h, k, per_vertex=True, nthreads=8)
+        low = pv[keep].min()
+        A = keep & (pv == low)
+        rnd[A] = r
+        keep = keep & ~A
+        r += 1
+        if keep.any():
+            C = count(_induced(g, keep), k, nthreads=8)
+            best = max(best, float(C) / float(keep.sum()))
+    return best, r, rnd
 
 
 def features(n: int, ooff: np.ndarray, oidx: np.ndarray, round_rank_space: np.ndarray) -> np.ndarray:

@@ -73,6 +73,8 @@ _sigs = {
     "arb_count_batch_workspace": ([I64, I64, I32, I64], SZ),
     "arb_sparsify_workspace": ([I64, I64], SZ),
     "arb_approx_peel_workspace": ([I64, I64, I32], SZ),
+    "arb_peel_workspace": ([I64, I64, I32], SZ),
+    "arb_peel": ([P, I32, P, P, P, P, SZ, P], I32),
     "arb_approx_peel": ([P, I32, DBL, P, P, P, P, P, SZ, P], I32),
     "arb_sparsify": ([P, P, P, P, P, P, SZ, P], I32),
     "arb_colorful_estimate": ([ctypes.c_uint64, I32, I32], DBL),
@@ -285,6 +287,23 @@ def arb_approx_peel(ooff, oidx, k, eps=1.0, opts=None, stream=None):
                                 ctypes.byref(dens), ctypes.byref(rounds), _ptr(mask), _ptr(ws), ws.numel(),
                                 _stream(stream)), "arb_approx_peel")
     return dens.value, rounds.value, mask[:n]
+
+
+def arb_peel_workspace(n: int, m: int, k: int) -> int:
+    return int(_lib.arb_peel_workspace(n, m, int(k)))
+
+
+def arb_peel(ooff, oidx, k, stream=None):
+    """arb-peel: (best density, rounds, round of each vertex int32[n] in rank space)."""
+    dg = _ocsr(ooff, oidx)
+    n = dg.n
+    rnd = torch.empty(max(n, 1), dtype=torch.int32, device=ooff.device)
+    ws = _ws(_lib.arb_peel_workspace(n, dg.m, int(k)), ooff.device)
+    dens = ctypes.c_double(0.0)
+    rounds = ctypes.c_int64(0)
+    _check(_lib.arb_peel(ctypes.byref(dg), int(k), ctypes.byref(dens), ctypes.byref(rounds), _ptr(rnd), _ptr(ws),
+                         ws.numel(), _stream(stream)), "arb_peel")
+    return dens.value, rounds.value, rnd[:n]
 
 
 def arb_colorful_estimate(count: int, colors: int, k: int) -> float:

@@ -380,10 +380,20 @@ extern "C" int arb_check_oriented(const arb_ocsr *dg, void *ws, size_t ws_bytes,
     return rc;
 }
 
-static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *per_root_out,
-                      uint64_t *work_out, const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s) {
+// roff/ridx (nullable): the candidate set of each root in place of N+(v) -- any sorted
+// set of vertices whose every (k-1)-clique, with the root, is a k-clique to count
+// (arb-peel's updates); the workspace must then be sized for max(m, rnnz) arcs.
+int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *per_root_out,
+                     uint64_t *work_out, const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s,
+                     const int64_t *roff, const int32_t *ridx, int64_t rnnz) {
     if (!ocsr_ok(dg) || !total_dev || !ws) return ARB_EINVAL;
     if (k < 1 || k > ARB_MAX_K) return ARB_EINVAL;
+    if (roff && (!ridx || k < 3)) return ARB_EINVAL;
+    const int64_t mw = roff && rnnz > dg->m ? rnnz : dg->m;     // arcs the item arrays must hold
+    if (!roff) {
+        roff = dg->offsets;
+        ridx = dg->indices;
+    }
     arb_count_opts opts;
     arb_count_default_opts(&opts);
     if (opts_in) opts = *opts_in;
@@ -394,7 +404,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     if (opts.bitmap_max_span < 0) return ARB_EINVAL;
     if (opts.split_min_degree < 0 || !(opts.split_min_cost >= 0.f)) return ARB_EINVAL;
     const int64_t n = dg->n, m = dg->m;
-    if (ws_bytes < arb_count_workspace(n, m, k)) return ARB_EWORKSPACE;
+    if (ws_bytes < arb_count_workspace(n, mw, k)) return ARB_EWORKSPACE;
     unsigned long long *total = reinterpret_cast<unsigned long long *>(total_dev);
     unsigned long long *pv = reinterpret_cast<unsigned long long *>(per_vertex);
     unsigned long long *work = reinterpret_cast<unsigned long long *>(work_out);
@@ -417,7 +427,7 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
 
     Carver cv(ws);
     CountWs w;
-    carve_count(cv, n, m, k, &w);
+    carve_count(cv, n, mw, k, &w);
     if ((rc = fill_i32(w.err, 0, 4, s))) return rc;
     if ((rc = fill_i32(w.heads, 0, 16, s))) return rc;
     if ((rc = fill_i64(w.seg, 0, 16, s))) return rc;
@@ -430,13 +440,13 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     }
     const int split_deg = work ? 0 : opts.split_min_degree;
     const float split_cost = work ? 0.f : opts.split_min_cost;
-    k_root_keys<<<gb, 256, 0, s>>>(n, dg->offsets, k, lcost, split_deg, split_cost, w.dbig, w.key, w.val, w.parts);
+    k_root_keys<<<gb, 256, 0, s>>>(n, roff, k, lcost, split_deg, split_cost, w.dbig, w.key, w.val, w.parts);
     ARB_CHECK_LAUNCH();
     if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, n, kCostBits + 3, w.radix_ws, s))) return rc;
-    k_sorted_units<<<gb, 256, 0, s>>>(n, dg->offsets, w.key, w.val, w.parts, w.ucnt);
+    k_sorted_units<<<gb, 256, 0, s>>>(n, roff, w.key, w.val, w.parts, w.ucnt);
     ARB_CHECK_LAUNCH();
     if ((rc = exclusive_scan_i64(w.ucnt, w.ucnt, n, w.scan_ws, s))) return rc;
-    k_expand<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, dg->offsets, dg->indices, w.val, w.parts, w.ucnt,
+    k_expand<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, roff, ridx, w.val, w.parts, w.ucnt,
                                                          w.iroot, w.ichild);
     ARB_CHECK_LAUNCH();
     k_segments<<<gb, 256, 0, s>>>(n, w.key, w.ucnt, w.seg);
@@ -462,6 +472,8 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
         CountArgs a;
         a.off = dg->offsets;
         a.idx = dg->indices;
+        a.roff = roff;
+        a.ridx = ridx;
         a.n = n;
         a.m = m;
         a.k = k;
@@ -517,6 +529,8 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
         CountArgs a;
         a.off = dg->offsets;
         a.idx = dg->indices;
+        a.roff = roff;
+        a.ridx = ridx;
         a.n = n;
         a.m = m;
         a.k = k;
@@ -549,6 +563,12 @@ static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *
     k_finish<<<1, 64, 0, s>>>(w.err, total);
     ARB_CHECK_LAUNCH();
     return ARB_OK;
+}
+
+static int count_impl(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *per_root_out,
+                      uint64_t *work_out, const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s) {
+    return count_with_roots(dg, k, total_dev, per_vertex, per_root_out, work_out, opts_in, ws, ws_bytes, s, nullptr,
+                            nullptr, 0);
 }
 
 extern "C" int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,

@@ -148,15 +148,15 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
         const int64_t it = beg + (int64_t)T->pop;
         if (it >= end) break;
         const int32_t root = a.item_root[it];
-        const int64_t s0 = a.off[root];
-        const int64_t d64 = a.off[root + 1] - s0;
+        const int64_t s0 = a.roff[root];
+        const int64_t d64 = a.roff[root + 1] - s0;
         if (d64 > b.dbig || d64 > kBigMax || a.item_child[it] != -1) {
             if (tlid == 0) atomicOr(a.err, 1);
             continue;
         }
         const int d = (int)d64, W = (d + 31) / 32;
         const int need = a.k - 1;                       // 2 or 3
-        for (int i = tlid; i < d; i += TT) T->S[i] = a.idx[s0 + i];
+        for (int i = tlid; i < d; i += TT) T->S[i] = a.ridx[s0 + i];
         for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
         if constexpr (PV)
             for (int i = tlid; i < d; i += TT) T->cnt[i] = 0ull;

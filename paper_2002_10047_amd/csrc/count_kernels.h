@@ -255,8 +255,10 @@ __device__ __forceinline__ unsigned long long team_sum(AS3<Lds> *T, unsigned lon
 }
 
 struct CountArgs {
-    const int64_t *off;
+    const int64_t *off;            // directed CSR (rank space)
     const int32_t *idx;
+    const int64_t *roff;           // root candidate sets: N+(v) (= off/idx), or any sorted subset
+    const int32_t *ridx;           //   of the graph's vertices per root (peeling updates)
     int64_t n;
     int64_t m;
     int k;
@@ -559,19 +561,19 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     }
     int need;
     if (child < 0) {
-        const int64_t s0 = a.off[root];
-        const int64_t d = a.off[root + 1] - s0;
+        const int64_t s0 = a.roff[root];
+        const int64_t d = a.roff[root + 1] - s0;
         if (d > Lds::D) {
             if (tlid == 0) atomicOr(a.err, 1);
             return 0;
         }
-        for (int i = tlid; i < d; i += TT) T->S[i] = a.idx[s0 + i];
+        for (int i = tlid; i < d; i += TT) T->S[i] = a.ridx[s0 + i];
         if (tlid == 0) T->d = (int)d;
         need = a.k - 1;
     } else {
         // S = N+(root) ∩ N+(child): wave 0 walks N+(child) and binary-searches N+(root)
         if (wv == 0) {
-            const int64_t rs = a.off[root], re = a.off[root + 1];
+            const int64_t rs = a.roff[root], re = a.roff[root + 1];
             const int64_t cs = a.off[child], ce = a.off[child + 1];
             int cntS = 0;
             for (int64_t b = cs; b < ce; b += 64) {
@@ -583,9 +585,9 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
                     int64_t lo = rs, hi = re;
                     while (lo < hi) {
                         int64_t mid = lo + ((hi - lo) >> 1);
-                        if (a.idx[mid] < w) lo = mid + 1; else hi = mid;
+                        if (a.ridx[mid] < w) lo = mid + 1; else hi = mid;
                     }
-                    hit = lo < re && a.idx[lo] == w;
+                    hit = lo < re && a.ridx[lo] == w;
                 }
                 uint64_t m = __ballot(hit);
                 int pos = cntS + __popcll(m & below);
@@ -886,6 +888,11 @@ inline int64_t big_teams(int64_t m) {
 inline int64_t big_team_words(int dbig) { return (int64_t)dbig * ((dbig + 31) / 32); }
 
 int launch_count_big(bool pv, bool instr, const CountArgs &a, const BigArgs &b, unsigned grid, hipStream_t s);
+
+// count.hip: the counting driver with optional per-root candidate sets (see there)
+int count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *per_root_out,
+                     uint64_t *work_out, const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s,
+                     const int64_t *roff, const int32_t *ridx, int64_t rnnz);
 
 #define ARB_DECLARE_DEPTH(LM) \
     int launch_count_depth##LM(int tier, bool pv, bool instr, const CountArgs &a, unsigned grid, hipStream_t s);

@@ -29,3 +29,18 @@ def test_approx_peel_parity(arb, orc, name, mk):
         dr, rr, mr = orc.approx_peel(g, k, eps)
         assert (d, r) == (dr, rr), (name, k, eps)
         assert np.array_equal(mask.cpu().numpy()[rank] != 0, mr), (name, k, eps)
+
+
+@pytest.mark.parametrize("name,mk", [("c1", lambda: gg.config_graph("c1")), ("gnp", lambda: gg.gnp(400, 0.06, 4)),
+                                     ("rmat11", lambda: gg.rmat(11, 20000, seed=4)),
+                                     ("sbm", lambda: gg.sbm2(600, 0.1, 0.3, 3)), ("K20", lambda: gg.complete(20))])
+def test_exact_peel_parity(arb, orc, name, mk):
+    g = mk()
+    off, idx = arb.to_device_csr(g)
+    o = arb.arb_orient(off, idx)
+    rank = o["rank"].cpu().numpy()
+    for k in (3, 4):
+        d, r, rnd = arb.arb_peel(o["ooff"], o["oidx"], k)
+        dr, rr, rndr = orc.peel(g, k)
+        assert (d, r) == (dr, rr), (name, k, d, dr, r, rr)
+        assert np.array_equal(rnd.cpu().numpy()[rank], rndr), (name, k)

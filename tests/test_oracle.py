@@ -445,3 +445,24 @@ def test_approx_peel_closed_form_and_guarantee(orc):
             if mask.any():
                 h = orc._induced(g, mask)
                 assert orc.count(h, k) / mask.sum() == d
+
+
+def test_peel_closed_forms_and_guarantee(orc):
+    # K_n: all counts equal, one round, density C(n,k)/n
+    for n, k in ((10, 3), (8, 4)):
+        d, r, rnd = orc.peel(gg.complete(n), k)
+        assert r == 1 and d == math.comb(n, k) / n and np.all(rnd == 0)
+    # K_6 plus a pendant path 5-6-7: round 0 removes 6, 7 (no triangles), round 1 the
+    # clique; best density = C(6,3)/6 after round 0
+    u = [a for a in range(6) for b in range(a + 1, 6)] + [5, 6]
+    v = [b for a in range(6) for b in range(a + 1, 6)] + [6, 7]
+    g = gg.csr_from_pairs(8, np.array(u), np.array(v))
+    d, r, rnd = orc.peel(g, 3)
+    assert rnd.tolist() == [1] * 6 + [0, 0] and r == 2 and d == 20 / 6
+    # the 1/k guarantee against the exact densest subgraph (brute force)
+    for seed in (1, 2, 3):
+        g = gg.gnp(13, 0.5, seed)
+        for k in (3, 4):
+            opt = _densest_brute(g, k)
+            d, r, rnd = orc.peel(g, k)
+            assert opt / k - 1e-12 <= d <= opt + 1e-12, (seed, k, d, opt)
