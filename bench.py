@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--tune-cache", default="", help="tuned-options cache file (default: the package's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (profiling runs)")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the studies after the roofline (sparsification, orderings, peeling), so that a "
+                         "kernel trace of the run holds only the launches the roofline averages")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (counter calibration)")
@@ -415,6 +418,13 @@ def main():
             per_k[str(k)]["alu_frac"] = u["alu"] / t / 1e12 / PEAK_ALU_TOPS
             per_k[str(k)]["lds_GBs"] = u["lds"] / t / 1e9
             per_k[str(k)]["hbm_GBs"] = u["hbm"] / t / 1e9
+
+    if a.no_studies:
+        if not a.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(g, ks, a.cpu_seconds)
+        copy_calibration(a, torch)
+        print(json.dumps(out), flush=True)
+        return
 
     # ---------------------------------------------------------------- colorful sparsification
     # approximate counts (Sec. 3.3): sparsify with c colours, orient and count the sparsified
