@@ -92,9 +92,10 @@ struct TeamLds {
     static constexpr int HB = __builtin_ctz(HS);
     static constexpr int TW = TW_;
     // per-wave pair ring (power of two): holds a whole row on top of a partial chunk.  An
-    // entry is (x << 16 | y), or in the 768-tier (slot << 10 | y) with x kept in a 64-slot
-    // table of the wave's recent non-empty rows: fewer than 64 entries are ever left over
-    // from earlier rows, so a slot is reused only after its entries were taken
+    // entry is (row << 16 | member), or in the 768-tier (slot << 10 | member) with the row
+    // kept in a 64-slot table of the wave's recent non-empty rows: fewer than 64 entries
+    // are ever left over from earlier rows, so a slot is reused only after its entries
+    // were taken
     static constexpr int RING = pow2_at_least(D + 64);
     static constexpr bool CR = W == 24;
     using RingT = typename std::conditional<CR, uint16_t, uint32_t>::type;
@@ -217,6 +218,20 @@ __device__ __forceinline__ uint32_t gtmask(int z, int w) {
     return w < zw ? 0u : (w > zw ? ~0u : hi);
 }
 
+// bits of word w that stand for local ids less than z
+__device__ __forceinline__ uint32_t ltmask(int z, int w) {
+    int zw = z >> 5, zb = z & 31;
+    return w > zw ? 0u : (w < zw ? ~0u : ((1u << zb) - 1u));
+}
+
+// Bit rows of the induced subgraph: with subtrees below the pairs (LMAX >= 2) or per-vertex
+// counts, row x holds all of x's neighbours in S (symmetric), and the pairs (x, y), x < y,
+// are dealt grouped by their larger end y (column order: y's row below y).  Pairs sharing
+// y draw their candidate sets from the same row, so the 64 lanes that take a step's pairs
+// get subtrees of similar size.  Otherwise (k = 4 without per-vertex counts) row x holds
+// only x's neighbours above x and the pairs are dealt by rows.
+template <bool PV, int LMAX> constexpr bool sym_rows() { return PV || LMAX >= 2; }
+
 template <int TW, int TPB>
 __device__ __forceinline__ void team_sync() {
     if constexpr (TPB == 1) {
@@ -315,12 +330,12 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
         out.nodes += c;
     }
     if constexpr (L == 2 && !PV) {
-        // leaf level on upper rows: row z has no bits below z, so the AND starts at the
-        // vector holding z's word (the row's words below z's are zero)
+        // leaf level: member z of J adds the edges from z to the members of J above z.
+        // Members are taken in ascending order, so the bits of z's word still to be taken
+        // are J's members above z in that word; the AND covers that word and the words
+        // above it (the vectors below z's are never loaded)
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            constexpr int Q = Lds::Q;
-            const int v0 = (w / Q) * Q;
             uint32_t bits = J.w[w];
             if constexpr (Lds::TW >= 16) {
                 // 16-wave teams: 128 VGPRs, one member per step
@@ -329,10 +344,9 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
                     bits &= bits - 1;
                     uint32_t r[W];
                     load_row<W, 0, Lds>(T, z, r);
-                    unsigned c = 0;
+                    unsigned c = __popc(bits & r[w]);
 #pragma unroll
-                    for (int v = 0; v < W; ++v)
-                        if (v >= v0) c += __popc(J.w[v] & r[v]);
+                    for (int v = w + 1; v < W; ++v) c += __popc(J.w[v] & r[v]);
                     out.c += c;
                 }
             } else {
@@ -340,19 +354,18 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
                     // two members per step, so that the second row's loads overlap the first's
                     const int z1 = w * 32 + __ffs(bits) - 1;
                     bits &= bits - 1;
+                    const uint32_t above1 = bits;
                     const bool two = bits != 0;
                     const int z2 = two ? w * 32 + __ffs(bits) - 1 : z1;
                     bits &= bits - 1;
                     uint32_t r1[W], r2[W];
                     load_row<W, 0, Lds>(T, z1, r1);
                     load_row<W, 0, Lds>(T, z2, r2);
-                    unsigned c1 = 0, c2 = 0;
+                    unsigned c1 = __popc(above1 & r1[w]), c2 = __popc(bits & r2[w]);
 #pragma unroll
-                    for (int v = 0; v < W; ++v) {
-                        if (v >= v0) {
-                            c1 += __popc(J.w[v] & r1[v]);
-                            c2 += __popc(J.w[v] & r2[v]);
-                        }
+                    for (int v = w + 1; v < W; ++v) {
+                        c1 += __popc(J.w[v] & r1[v]);
+                        c2 += __popc(J.w[v] & r2[v]);
                     }
                     out.c += c1 + (two ? c2 : 0u);
                 }
@@ -381,7 +394,7 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
         } else {
             Bits<W> K;
 #pragma unroll
-            for (int w = 0; w < W; ++w) K.w[w] = PV ? (J.w[w] & rz[w] & gtmask(z, w)) : (J.w[w] & rz[w]);
+            for (int w = 0; w < W; ++w) K.w[w] = R[w] & rz[w];   // R: J's members above z
             Acc sub;
             if constexpr (L - 1 <= 3) sub = dfs_inline<W, PV, INSTR, L - 1, Lds>(T, K);
             else sub = dfs_body<W, PV, INSTR, L - 1, Lds>(T, K);
@@ -419,6 +432,7 @@ __device__ __forceinline__ Acc do_pair(AS3<Lds> *T, int x, int y, int need) {
     uint32_t rx[W], ry[W];
     load_row<W, 0, Lds>(T, x, rx);
     load_row<W, 0, Lds>(T, y, ry);
+    constexpr bool SYM = sym_rows<PV, LMAX>();
     Acc out{0ull, INSTR ? 1ull : 0ull};
     if (need == 1 || LMAX < 2) {
         if constexpr (PV) {
@@ -435,14 +449,14 @@ __device__ __forceinline__ Acc do_pair(AS3<Lds> *T, int x, int y, int need) {
         } else {
             unsigned c = 0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) c += __popc(rx[w] & ry[w]);
+            for (int w = 0; w < W; ++w) c += __popc(rx[w] & ry[w] & (SYM ? gtmask(y, w) : ~0u));
             out.c = c;
         }
         return out;
     }
     Bits<W> J;
 #pragma unroll
-    for (int w = 0; w < W; ++w) J.w[w] = PV ? (rx[w] & ry[w] & gtmask(y, w)) : (rx[w] & ry[w]);
+    for (int w = 0; w < W; ++w) J.w[w] = rx[w] & ry[w] & (SYM ? gtmask(y, w) : ~0u);
     const Acc sub = dfs_dispatch<W, LMAX, PV, INSTR, Lds>(T, J, need);
     if constexpr (PV) {
         if (sub.c) {
@@ -464,7 +478,7 @@ constexpr int kGatherUnroll = 8;   // independent 4-byte loads in flight per lan
 // them into one element stream and consumes it 64 * kGatherUnroll entries per step, each
 // lane walking its own cursor through the list table in LDS, so that short and long
 // lists alike keep kGatherUnroll loads per lane in flight.
-template <int W, bool PV, class Lds>
+template <int W, bool PV, bool SYM, class Lds>
 __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, int d, int need, int g0, int gstep,
                                              int32_t first, int32_t last, bool bmode, int wv, int lane,
                                              unsigned long long &mine, unsigned long long &words) {
@@ -529,7 +543,7 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
                     }
                 } else {
                     lds_or(&T->rows[i * Lds::RS + (j >> 5)], 1u << (j & 31));
-                    if constexpr (PV) lds_or(&T->rows[j * Lds::RS + (i >> 5)], 1u << (i & 31));
+                    if constexpr (SYM) lds_or(&T->rows[j * Lds::RS + (i >> 5)], 1u << (i & 31));
                 }
             }
         }
@@ -646,31 +660,34 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
         // split its lists
         const int g0 = need == 2 ? part + P * wv : wv, gstep = need == 2 ? P * TW : TW;
         unsigned long long words = 0;
-        gather_lists<W, PV, Lds>(T, a, d, need, g0, gstep, first, last, bmode, wv, lane, mine, words);
+        gather_lists<W, PV, sym_rows<PV, LMAX>(), Lds>(T, a, d, need, g0, gstep, first, last, bmode, wv, lane, mine, words);
         if constexpr (INSTR) gather += words;
         if constexpr (INSTR) {
             if (tlid == 0) nodes += (unsigned long long)d;     // depth-1 nodes
         }
         if (need >= 3) {
             team_sync<TW, TPB>();
-            // pairs (x, y), y > x adjacent, spread over the lanes through the wave's ring.  When subtrees lie below the
-            // pairs (pneed >= 2) the waves of a team claim rows in ascending order (largest
-            // rows first) from a team counter, one claim ahead; otherwise rows are dealt
-            // round-robin
+            // pairs (x, y), x < y adjacent, spread over the lanes through the wave's ring,
+            // a row r at a time: r = x with its members above x (upper rows), or r = y with
+            // its members below y (symmetric rows).  When subtrees lie below the pairs
+            // (pneed >= 2) the waves of a team claim rows in ascending order from a team
+            // counter, one claim ahead; otherwise rows are dealt round-robin
+            constexpr bool SYM = sym_rows<PV, LMAX>();
             using RingT = typename Lds::RingT;
             AS3<RingT> *ring = T->q.ring[wv];
             unsigned head = 0, tail = 0;          // ring positions [head, tail) not yet taken
             const int pneed = need - 2;
             unsigned slot = 0;
             auto take = [&](uint32_t p) {
-                int px, py;
+                int pr, pm;          // the entry's row and member
                 if constexpr (Lds::CR) {
-                    px = T->xs[wv][p >> 10];
-                    py = (int)(p & 1023u);
+                    pr = T->xs[wv][p >> 10];
+                    pm = (int)(p & 1023u);
                 } else {
-                    px = (int)(p >> 16);
-                    py = (int)(p & 0xffffu);
+                    pr = (int)(p >> 16);
+                    pm = (int)(p & 0xffffu);
                 }
+                const int px = SYM ? pm : pr, py = SYM ? pr : pm;
                 const Acc r = do_pair<W, LMAX, PV, INSTR, Lds>(T, px, py, pneed);
                 mine += r.c;
                 nodes += r.nodes;
@@ -680,12 +697,12 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
             if (dyn && lane == 0)
                 claim = __hip_atomic_fetch_add(&T->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             while (true) {
-                const int x = part + P * xi;
-                if (x >= d) break;
+                const int row = part + P * xi;
+                if (row >= d) break;
                 uint32_t bits = 0;
                 if (lane < W) {
-                    bits = T->rows[x * Lds::RS + lane];
-                    if constexpr (PV) bits &= gtmask(x, lane);
+                    bits = T->rows[row * Lds::RS + lane];
+                    if constexpr (SYM) bits &= ltmask(row, lane);
                 }
                 const unsigned c = __popc(bits);
                 unsigned pre = c;
@@ -700,11 +717,11 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
                 if constexpr (Lds::CR) {
                     if (end != tail) {
                         slot = (slot + 1) & 63u;
-                        if (lane == 0) T->xs[wv][slot] = (uint16_t)x;
+                        if (lane == 0) T->xs[wv][slot] = (uint16_t)row;
                     }
                     tag = slot << 10;
                 } else {
-                    tag = (uint32_t)x << 16;
+                    tag = (uint32_t)row << 16;
                 }
                 while (bits) {
                     const int b = __ffs(bits) - 1;
