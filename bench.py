@@ -260,6 +260,7 @@ def main():
         schedules[name] = per_k
     schedules["plain"] = {k: arb.count_opts(schedule=arb.ARB_SCHED_PLAIN) for k in ks}
     log(f"tuning took {time.time() - t_tune:.1f}s")
+    arb.arb_profile_enable(True)      # the kernel timings cover the timed steps only, not tuning
 
     def step(name):
         oo = arb.arb_orient(off, idx, eps=a.eps)

@@ -10,6 +10,8 @@
 
 namespace arb {
 
+constexpr int kBigGatherUnroll = 8;   // independent 4-byte list loads in flight per lane
+
 template <bool PV>
 struct BigLds {
     static constexpr int TW = 16;
@@ -65,11 +67,11 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int
         int64_t c_end = lt[0].end;
         int64_t c_delta = lt[0].delta;
         int c_row = lt[0].row;
-        for (int64_t base = 0; base < total; base += 64 * kGatherUnroll) {
-            int32_t w[kGatherUnroll];
-            int r[kGatherUnroll];
+        for (int64_t base = 0; base < total; base += 64 * kBigGatherUnroll) {
+            int32_t w[kBigGatherUnroll];
+            int r[kBigGatherUnroll];
 #pragma unroll
-            for (int q = 0; q < kGatherUnroll; ++q) {
+            for (int q = 0; q < kBigGatherUnroll; ++q) {
                 const int64_t pos = base + 64 * q + lane;
                 w[q] = 0x7fffffff;
                 r[q] = 0;
@@ -85,7 +87,7 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int
                 }
             }
 #pragma unroll
-            for (int q = 0; q < kGatherUnroll; ++q) {
+            for (int q = 0; q < kBigGatherUnroll; ++q) {
                 const int j = member_find(T, w[q], first, last, false);
                 if (j < 0) continue;
                 const int i = r[q];

@@ -471,13 +471,15 @@ __device__ __forceinline__ Acc do_pair(AS3<Lds> *T, int x, int y, int need) {
 
 // ------------------------------------------------------------------ second level
 
-constexpr int kGatherUnroll = 8;   // independent 4-byte loads in flight per lane
+// independent 4-byte loads in flight per lane: 8, or 4 in the 128-tier, whose kernels
+// then fit 5 waves per SIMD (measured faster there)
+template <int W> constexpr int gather_unroll() { return W == 4 ? 4 : 8; }
 
 // Second level of the recursion: for the lists N+(S[i]), i = g0, g0 + gstep, ... < d,
 // keep the entries that are members of S.  A wave takes 64 lists at a time, concatenates
-// them into one element stream and consumes it 64 * kGatherUnroll entries per step, each
+// them into one element stream and consumes it 64 * gather_unroll entries per step, each
 // lane walking its own cursor through the list table in LDS, so that short and long
-// lists alike keep kGatherUnroll loads per lane in flight.
+// lists alike keep gather_unroll loads per lane in flight.
 template <int W, bool PV, bool SYM, class Lds>
 __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, int d, int need, int g0, int gstep,
                                              int32_t first, int32_t last, bool bmode, int wv, int lane,
@@ -511,11 +513,12 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
         int64_t c_end = lt[0].end;
         int64_t c_delta = lt[0].delta;
         int c_row = lt[0].row;
-        for (int64_t base = 0; base < total; base += 64 * kGatherUnroll) {
-            int32_t w[kGatherUnroll];
-            int r[kGatherUnroll];
+        constexpr int GU = gather_unroll<W>();
+        for (int64_t base = 0; base < total; base += 64 * GU) {
+            int32_t w[GU];
+            int r[GU];
 #pragma unroll
-            for (int q = 0; q < kGatherUnroll; ++q) {
+            for (int q = 0; q < GU; ++q) {
                 const int64_t pos = base + 64 * q + lane;
                 w[q] = 0x7fffffff;
                 r[q] = 0;
@@ -531,7 +534,7 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
                 }
             }
 #pragma unroll
-            for (int q = 0; q < kGatherUnroll; ++q) {
+            for (int q = 0; q < GU; ++q) {
                 const int j = member_find(T, w[q], first, last, bmode);
                 if (j < 0) continue;
                 const int i = r[q];
@@ -771,8 +774,16 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     return mine;
 }
 
+// Waves per SIMD the register allocation must allow: in the two smallest tiers at depth
+// <= 2 the latency of the list reads dominates, and more resident waves hide more of it
+// (measured: 6 and 5 beat the 4 that their register use would give)
+template <int W, bool PV, int LMAX> constexpr int tier_min_waves() {
+    return (PV || LMAX > 2) ? 1 : (W == 2 ? 6 : (W == 4 ? 5 : 1));
+}
+
 template <int W, int LMAX, bool PV, bool INSTR>
 __global__ void __launch_bounds__((tier_threads<W, PV, LMAX>()))
+__attribute__((amdgpu_waves_per_eu(tier_min_waves<W, PV, LMAX>())))
 k_count(CountArgs a) {
     using Cfg = TierCfg<W, PV, LMAX>;
     constexpr int TW = Cfg::TW, TPB = Cfg::TPB;
