@@ -333,7 +333,9 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
         // leaf level: member z of J adds the edges from z to the members of J above z.
         // Members are taken in ascending order, so the bits of z's word still to be taken
         // are J's members above z in that word; the AND covers that word and the words
-        // above it (the vectors below z's are never loaded)
+        // above it (the vectors below z's are never loaded).  The leaf's sum is below
+        // 768 * 768 / 2, so it is kept in 32 bits
+        unsigned leaf = 0;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             uint32_t bits = J.w[w];
@@ -344,10 +346,9 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
                     bits &= bits - 1;
                     uint32_t r[W];
                     load_row<W, 0, Lds>(T, z, r);
-                    unsigned c = __popc(bits & r[w]);
+                    leaf += __popc(bits & r[w]);
 #pragma unroll
-                    for (int v = w + 1; v < W; ++v) c += __popc(J.w[v] & r[v]);
-                    out.c += c;
+                    for (int v = w + 1; v < W; ++v) leaf += __popc(J.w[v] & r[v]);
                 }
             } else {
                 while (bits) {
@@ -361,16 +362,18 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
                     uint32_t r1[W], r2[W];
                     load_row<W, 0, Lds>(T, z1, r1);
                     load_row<W, 0, Lds>(T, z2, r2);
-                    unsigned c1 = __popc(above1 & r1[w]), c2 = __popc(bits & r2[w]);
+                    unsigned c2 = __popc(bits & r2[w]);
+                    leaf += __popc(above1 & r1[w]);
 #pragma unroll
                     for (int v = w + 1; v < W; ++v) {
-                        c1 += __popc(J.w[v] & r1[v]);
+                        leaf += __popc(J.w[v] & r1[v]);
                         c2 += __popc(J.w[v] & r2[v]);
                     }
-                    out.c += c1 + (two ? c2 : 0u);
+                    leaf += two ? c2 : 0u;
                 }
             }
         }
+        out.c += leaf;
         return out;
     }
     uint32_t R[W];
