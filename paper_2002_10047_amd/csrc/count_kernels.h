@@ -38,7 +38,7 @@ namespace arb {
 // (one 1024-lane block per CU keeps four waves on every SIMD within 128 VGPRs); deeper
 // walks and the per-vertex variants need more registers per lane and keep 8-wave teams.
 template <int W, bool PV, int LMAX> struct TierCfg {
-    static_assert(W <= 32, "the pair phase scans one row's words within 32 lanes");
+    static_assert(W <= 32 && W % 2 == 0, "the pair phase spreads a row over 64 lanes, W / 2 < 32 bits each");
     static constexpr bool wide = !PV && LMAX <= 2;
     static constexpr int TW = W == 2 ? 1 : (W <= 8 ? 4 : (wide && W >= 16 ? 16 : 8));
     static constexpr int TPB = W == 2 ? 4 : 1;
@@ -705,19 +705,30 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
             while (true) {
                 const int row = part + P * xi;
                 if (row >= d) break;
-                uint32_t bits = 0;
-                if (lane < W) {
-                    bits = T->rows[row * Lds::RS + lane];
-                    if constexpr (SYM) bits &= ltmask(row, lane);
+                // lane l expands bits [l B, l B + B) of the row, B = W / 2, so that a dense
+                // row costs at most B steps
+                constexpr int B = W / 2;
+                const int g = lane * B;
+                uint32_t bits;
+                {
+                    const AS3<uint32_t> *rw = &T->rows[row * Lds::RS + (g >> 5)];
+                    const int sh = g & 31;
+                    uint64_t win = rw[0];
+                    if (sh + B > 32) win |= (uint64_t)rw[1] << 32;
+                    bits = (uint32_t)(win >> sh) & (uint32_t)((1ull << B) - 1);
+                    if constexpr (SYM) {
+                        const int lim = row - g;     // members below the row's own id
+                        bits &= lim >= B ? ~0u : (lim <= 0 ? 0u : ((1u << lim) - 1u));
+                    }
                 }
                 const unsigned c = __popc(bits);
                 unsigned pre = c;
 #pragma unroll
-                for (int o = 1; o < 32; o <<= 1) {
+                for (int o = 1; o < 64; o <<= 1) {
                     const unsigned y = __shfl_up(pre, o, 64);
                     if (lane >= o) pre += y;
                 }
-                const unsigned end = tail + __shfl(pre, 31, 64);
+                const unsigned end = tail + __shfl(pre, 63, 64);
                 unsigned pos = tail + pre - c;
                 uint32_t tag;
                 if constexpr (Lds::CR) {
@@ -732,7 +743,7 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
                 while (bits) {
                     const int b = __ffs(bits) - 1;
                     bits &= bits - 1;
-                    ring[pos & (Lds::RING - 1)] = (RingT)(tag | (uint32_t)(lane * 32 + b));
+                    ring[pos & (Lds::RING - 1)] = (RingT)(tag | (uint32_t)(g + b));
                     ++pos;
                 }
                 wave_fence();
