@@ -23,6 +23,10 @@ enum : int32_t {
     kErrDegree = 32, kErrRowLong = 64, kErrLeft = 128, kErrBatch = 256
 };
 
+// rows of at most this many entries are walked by a group of 16 lanes, longer ones by a
+// whole wave
+constexpr int kGroupRow = 64;
+
 // ------------------------------------------------------------------ validation
 
 // One wave per vertex: offsets monotone, ids in range, no self-loop, strictly ascending
@@ -125,26 +129,37 @@ __global__ void k_peel_mark(int64_t n, const int32_t *deg, int32_t *rnd, int32_t
     }
 }
 
-// Each wave looks at 64 consecutive vertices; for every one removed in round r (ballot),
-// the whole wave walks its row and decrements neighbours still present.
+// Vertices are taken by groups of 16 lanes (four per wave); a vertex removed in round r
+// lowers each neighbour still present by one, its row walked by its group when it has at
+// most kGroupRow entries, else by the whole wave after the groups' short rows.
 // act[0] < 0: nothing was present at the start of round r (the round is a no-op)
 __global__ void k_peel_decrement(int64_t n, const int64_t *off, const int32_t *idx, int32_t *deg,
                                  const int32_t *rnd, int r, const int64_t *act) {
     if (act[0] < 0) return;
-    const int lane = threadIdx.x & 63;
-    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-        int64_t v = base + lane;
-        bool hit = v < n && rnd[v] == r;
-        uint64_t mask = __ballot(hit);
-        while (mask) {
-            int b = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            int64_t x = base + b;
-            int64_t s = off[x], e = off[x + 1];
-            for (int64_t p = s + lane; p < e; p += 64) {
-                int32_t u = idx[p];
+    const int lane = threadIdx.x & 63, sl = lane & 15;
+    int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (; grp - (lane >> 4) < n; grp += ngrp) {      // while the wave's first group has a vertex
+        int64_t b = 0, e = 0;
+        bool heavy = false;
+        if (grp < n && rnd[grp] == r) {
+            b = off[grp];
+            e = off[grp + 1];
+            heavy = e - b > kGroupRow;
+            if (!heavy) {
+                for (int64_t p = b + sl; p < e; p += 16) {
+                    const int32_t u = idx[p];
+                    if (rnd[u] == kPresent) atomicSub(&deg[u], 1);
+                }
+            }
+        }
+        uint64_t hm = __ballot(heavy && sl == 0);
+        while (hm) {
+            const int src = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const int64_t hb = __shfl(b, src, 64), he = __shfl(e, src, 64);
+            for (int64_t p = hb + lane; p < he; p += 64) {
+                const int32_t u = idx[p];
                 if (rnd[u] == kPresent) atomicSub(&deg[u], 1);
             }
         }
@@ -380,79 +395,173 @@ __global__ void k_rank_scatter(int64_t n, const int32_t *inv, int32_t *rank) {
 
 // ------------------------------------------------------------------ directing
 
-// One wave per vertex: number of neighbours of higher rank, stored at the vertex's rank.
+// Vertices of degree <= 64 are taken by groups of 16 lanes (four per wave): most rows are
+// short, and a whole wave per row would leave most lanes idle and only one row's chain of
+// dependent loads per wave in flight.  A longer row is taken by the whole wave after its
+// groups' short rows.
+// Number of neighbours of higher rank, stored at the vertex's rank.
 __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *rank,
                             int64_t *outdeg) {
-    const int lane = threadIdx.x & 63;
-    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t v = wave; v < n; v += nwaves) {
-        int32_t rv = rank[v];
-        int64_t c = 0;
-        for (int64_t p = off[v] + lane; p < off[v + 1]; p += 64) c += rank[idx[p]] > rv;
+    const int lane = threadIdx.x & 63, sl = lane & 15;
+    int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (; grp - (lane >> 4) < n; grp += ngrp) {      // while the wave's first group has a vertex
+        int32_t rv = 0;
+        int64_t b = 0, e = 0, c = 0;
+        bool light = false, heavy = false;
+        if (grp < n) {
+            b = off[grp];
+            e = off[grp + 1];
+            rv = rank[grp];
+            light = e - b <= kGroupRow;
+            heavy = !light;
+        }
+        if (light)
+            for (int64_t p = b + sl; p < e; p += 16) c += rank[idx[p]] > rv;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
-        if (lane == 0) outdeg[rv] = c;
+        for (int o = 8; o > 0; o >>= 1) c += __shfl_xor(c, o, 16);
+        if (light && sl == 0) outdeg[rv] = c;
+        uint64_t hm = __ballot(heavy && sl == 0);
+        while (hm) {
+            const int src = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const int64_t hb = __shfl(b, src, 64), he = __shfl(e, src, 64);
+            const int32_t hr = __shfl(rv, src, 64);
+            int64_t hc = 0;
+            for (int64_t p = hb + lane; p < he; p += 64) hc += rank[idx[p]] > hr;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) hc += __shfl_xor(hc, o, 64);
+            if (lane == 0) outdeg[hr] = hc;
+        }
     }
 }
 
-// One wave per vertex: write the higher-ranked neighbours' ranks into the row of the
-// vertex's rank (order of the input row; sorted afterwards).
+// Write the higher-ranked neighbours' ranks into the row of the vertex's rank (order of
+// the input row; sorted afterwards).
 __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *rank,
                            const int64_t *ooff, int32_t *oidx) {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, sl = lane & 15, gsh = lane & 48;
+    const uint32_t below16 = (1u << sl) - 1u;
     const uint64_t below = lanes_below_mask();
-    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t v = wave; v < n; v += nwaves) {
-        int32_t rv = rank[v];
-        int64_t w = ooff[rv];
-        int64_t s = off[v], e = off[v + 1];
-        for (int64_t b = s; b < e; b += 64) {
-            int64_t p = b + lane;
-            int32_t ru = p < e ? rank[idx[p]] : -1;
-            bool keep = ru > rv;
-            uint64_t m = __ballot(keep);
-            if (keep) oidx[w + __popcll(m & below)] = ru;
-            w += __popcll(m);
+    int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (; grp - (lane >> 4) < n; grp += ngrp) {      // while the wave's first group has a vertex
+        int32_t rv = 0;
+        int64_t w = 0, b = 0, len = 0;
+        bool heavy = false;
+        if (grp < n) {
+            b = off[grp];
+            len = off[grp + 1] - b;
+            rv = rank[grp];
+            w = ooff[rv];
+            heavy = len > kGroupRow;
+        }
+        // short rows: the wave steps until its longest one is done (at most 4 steps)
+        const int64_t ll = heavy ? 0 : len;
+        int64_t lmax = ll;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int64_t y = __shfl_xor(lmax, o, 64);
+            lmax = y > lmax ? y : lmax;
+        }
+        int64_t wl = w;
+        for (int64_t q = 0; q < lmax; q += 16) {
+            const int32_t ru = (q + sl < ll) ? rank[idx[b + q + sl]] : -1;
+            const bool keep = ru > rv;
+            const uint32_t m = (uint32_t)(__ballot(keep) >> gsh) & 0xffffu;
+            if (keep) oidx[wl + __popc(m & below16)] = ru;
+            wl += __popc(m);
+        }
+        uint64_t hm = __ballot(heavy && sl == 0);
+        while (hm) {
+            const int src = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const int64_t hb = __shfl(b, src, 64), he = hb + __shfl(len, src, 64);
+            const int32_t hr = __shfl(rv, src, 64);
+            int64_t hw = __shfl(w, src, 64);
+            for (int64_t q = hb; q < he; q += 64) {
+                const int64_t p = q + lane;
+                const int32_t ru = p < he ? rank[idx[p]] : -1;
+                const bool keep = ru > hr;
+                const uint64_t m = __ballot(keep);
+                if (keep) oidx[hw + __popcll(m & below)] = ru;
+                hw += __popcll(m);
+            }
         }
     }
-}
-
-// Rows of at most 64 entries: one wave per row, each lane's destination is the number of
-// smaller entries (entries are distinct).  Also reduces the largest row length.
-__global__ void k_row_sort_small(int64_t n, const int64_t *ooff, int32_t *oidx, int64_t *stats) {
-    const int lane = threadIdx.x & 63;
-    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    int64_t dmax = 0;
-    for (int64_t r = wave; r < n; r += nwaves) {
-        int64_t s = ooff[r];
-        int d = (int)min<int64_t>(ooff[r + 1] - s, 0x7fffffff);
-        dmax = d > dmax ? d : dmax;
-        if (d <= 1 || d > 64) continue;
-        int32_t x = lane < d ? oidx[s + lane] : 0x7fffffff;
-        int pos = 0;
-        for (int j = 0; j < d; ++j) {
-            int32_t y = __shfl(x, j, 64);
-            pos += y < x;
-        }
-        if (lane < d) oidx[s + pos] = x;
-    }
-    if (stats && lane == 0 && dmax > 0) atomicMax((unsigned long long *)&stats[1], (unsigned long long)dmax);
 }
 
 constexpr int kMidRow = 2048;
 
-// Rows of 65..2048 entries: one block per row; each element's destination is the count
-// of smaller entries in the row, read back from LDS as broadcasts.
-__global__ void __launch_bounds__(256) k_row_sort_mid(int64_t n, const int64_t *ooff, int32_t *oidx) {
+// Rows of at most 16 entries: one group of 16 lanes per row, each lane's destination is
+// the number of smaller entries (entries are distinct); rows of 17..64 entries: the same
+// by the whole wave after its groups' short rows.  Longer rows are listed for the kernels
+// below (mid: 65..kMidRow entries, big: longer; cnt[0], cnt[1] entries), with one global
+// atomic per block and round.  Also reduces the largest row length.
+__global__ void __launch_bounds__(256) k_row_sort_small(int64_t n, const int64_t *ooff, int32_t *oidx,
+                                                        int64_t *stats, int32_t *mid, int32_t *big, int32_t *cnt) {
+    __shared__ int32_t lcnt[2], lbase[2];
+    const int lane = threadIdx.x & 63, sl = lane & 15;
+    int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    const int64_t first = ((int64_t)blockIdx.x * blockDim.x) >> 4;
+    int64_t dmax = 0;
+    for (int64_t base = first; base < n; base += ngrp, grp += ngrp) {   // uniform over the block
+        if (threadIdx.x < 2) lcnt[threadIdx.x] = 0;
+        __syncthreads();
+        int d = 0;
+        int64_t s = 0;
+        int slot = -1, which = 0;
+        if (grp < n) {
+            s = ooff[grp];
+            d = (int)min<int64_t>(ooff[grp + 1] - s, 0x7fffffff);
+            dmax = d > dmax ? d : dmax;
+            if (d > 64 && sl == 0) {
+                which = d <= kMidRow ? 0 : 1;
+                slot = atomicAdd(&lcnt[which], 1);
+            }
+        }
+        const bool mine = d >= 2 && d <= 16;
+        const int32_t x = (mine && sl < d) ? oidx[s + sl] : 0x7fffffff;
+        int pos = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) pos += __shfl(x, j, 16) < x;
+        if (mine && sl < d) oidx[s + pos] = x;
+        uint64_t wm = __ballot(d > 16 && d <= 64 && sl == 0);
+        while (wm) {
+            const int src = __ffsll((unsigned long long)wm) - 1;
+            wm &= wm - 1;
+            const int64_t ws = __shfl(s, src, 64);
+            const int wd = __shfl(d, src, 64);
+            const int32_t y = lane < wd ? oidx[ws + lane] : 0x7fffffff;
+            int wpos = 0;
+            for (int j = 0; j < wd; ++j) wpos += __shfl(y, j, 64) < y;
+            if (lane < wd) oidx[ws + wpos] = y;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 && lcnt[threadIdx.x] > 0)
+            lbase[threadIdx.x] = atomicAdd(&cnt[threadIdx.x], lcnt[threadIdx.x]);
+        __syncthreads();
+        if (slot >= 0) (which ? big : mid)[lbase[which] + slot] = (int32_t)grp;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t y = __shfl_xor(dmax, o, 64);
+        dmax = y > dmax ? y : dmax;
+    }
+    if (stats && lane == 0 && dmax > 0) atomicMax((unsigned long long *)&stats[1], (unsigned long long)dmax);
+}
+
+// Rows of 65..2048 entries (the list mid[0 .. *cnt)): one block per row; each element's
+// destination is the count of smaller entries in the row, read back from LDS as broadcasts.
+__global__ void __launch_bounds__(256) k_row_sort_mid(const int32_t *mid, const int32_t *cnt, const int64_t *ooff,
+                                                      int32_t *oidx) {
     __shared__ int32_t buf[kMidRow];
-    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+    const int32_t nl = *cnt;
+    for (int32_t l = blockIdx.x; l < nl; l += gridDim.x) {
+        const int32_t r = mid[l];
         const int64_t s = ooff[r];
-        const int64_t d64 = ooff[r + 1] - s;
-        if (d64 <= 64 || d64 > kMidRow) continue;
-        const int d = (int)d64;
+        const int d = (int)(ooff[r + 1] - s);
         for (int i = threadIdx.x; i < d; i += blockDim.x) buf[i] = oidx[s + i];
         __syncthreads();
         for (int i = threadIdx.x; i < d; i += blockDim.x) {
@@ -465,13 +574,16 @@ __global__ void __launch_bounds__(256) k_row_sort_mid(int64_t n, const int64_t *
     }
 }
 
-// Rows longer than 2048: one block per row, bitonic sort in LDS (padded to a power of two).
-__global__ void k_row_sort_big(int64_t n, const int64_t *ooff, int32_t *oidx, int32_t *err) {
+// Rows longer than 2048 (the list rows[0 .. *cnt)): one block per row, bitonic sort in
+// LDS (padded to a power of two).
+__global__ void k_row_sort_big(const int32_t *rows, const int32_t *cnt, const int64_t *ooff, int32_t *oidx,
+                               int32_t *err) {
     extern __shared__ int32_t big[];
-    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+    const int32_t nl = *cnt;
+    for (int32_t l = blockIdx.x; l < nl; l += gridDim.x) {
+        const int32_t r = rows[l];
         const int64_t s = ooff[r];
         const int64_t d64 = ooff[r + 1] - s;
-        if (d64 <= kMidRow) continue;
         if (d64 > ARB_MAX_ROW_SORT) {
             if (threadIdx.x == 0) atomicOr(err, (int32_t)kErrRowLong);
             continue;
@@ -539,7 +651,7 @@ static size_t carve_orient(Carver &c, int64_t n, int64_t nnz, OrientWs *w, int64
     w->deg = c.take<int32_t>(nn);
     w->rnd = c.take<int32_t>(nn);
     w->dap = c.take<int32_t>(nn);
-    w->err = c.take<int32_t>(4);
+    w->err = c.take<int32_t>(4);      // [0] error flags, [1], [2] list counters
     w->keys = c.take<uint32_t>(nn);
     w->keys_alt = c.take<uint32_t>(nn);
     w->vals = c.take<int32_t>(nn);
@@ -749,15 +861,19 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
     }
     k_rank_scatter<<<gb, 256, 0, s>>>(n, w.vals, rank);
     // directing
-    const unsigned gv = grid_for(n * 64, 256, 8192);
-    k_dir_count<<<gv, 256, 0, s>>>(n, g->offsets, g->indices, rank, w.outdeg);
+    const unsigned g16 = grid_for(n * 16, 256, 8192);
+    k_dir_count<<<g16, 256, 0, s>>>(n, g->offsets, g->indices, rank, w.outdeg);
     if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     if ((rc = exclusive_scan_i64(w.outdeg, out->offsets, n, w.scan_ws, s))) return rc;
-    k_dir_fill<<<gv, 256, 0, s>>>(n, g->offsets, g->indices, rank, out->offsets, out->indices);
-    k_row_sort_small<<<gv, 256, 0, s>>>(n, out->offsets, out->indices, stats);
-    k_row_sort_mid<<<grid_for(n, 1, 8192), 256, 0, s>>>(n, out->offsets, out->indices);
+    k_dir_fill<<<g16, 256, 0, s>>>(n, g->offsets, g->indices, rank, out->offsets, out->indices);
+    // rows longer than 64 are listed by the small-row sort (the rank-sort buffers are free
+    // by now; counters in err[1], err[2])
+    int32_t *mid_rows = w.vals_alt, *big_rows = reinterpret_cast<int32_t *>(w.keys_alt), *row_cnt = w.err + 1;
+    if ((rc = fill_i32(row_cnt, 0, 2, s))) return rc;
+    k_row_sort_small<<<g16, 256, 0, s>>>(n, out->offsets, out->indices, stats, mid_rows, big_rows, row_cnt);
+    k_row_sort_mid<<<grid_for(n, 1, 8192), 256, 0, s>>>(mid_rows, row_cnt, out->offsets, out->indices);
     k_row_sort_big<<<grid_for(n, 64, 256), 256, ARB_MAX_ROW_SORT * sizeof(int32_t), s>>>(
-        n, out->offsets, out->indices, w.err);
+        big_rows, row_cnt + 1, out->offsets, out->indices, w.err);
     if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     if (round_out) {
         k_copy_rounds<<<gb, 256, 0, s>>>(n, rnd, round_out);
