@@ -158,9 +158,13 @@ __global__ void k_peel_decrement(int64_t n, const int64_t *off, const int32_t *i
             const int src = __ffsll((unsigned long long)hm) - 1;
             hm &= hm - 1;
             const int64_t hb = __shfl(b, src, 64), he = __shfl(e, src, 64);
-            for (int64_t p = hb + lane; p < he; p += 64) {
-                const int32_t u = idx[p];
-                if (rnd[u] == kPresent) atomicSub(&deg[u], 1);
+            for (int64_t p0 = hb + lane; p0 < he; p0 += 256) {     // four loads in flight per lane
+                int32_t u[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = p0 + 64 * q < he ? idx[p0 + 64 * q] : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (u[q] >= 0 && rnd[u[q]] == kPresent) atomicSub(&deg[u[q]], 1);
             }
         }
     }
@@ -428,7 +432,13 @@ __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, c
             const int64_t hb = __shfl(b, src, 64), he = __shfl(e, src, 64);
             const int32_t hr = __shfl(rv, src, 64);
             int64_t hc = 0;
-            for (int64_t p = hb + lane; p < he; p += 64) hc += rank[idx[p]] > hr;
+            for (int64_t p0 = hb + lane; p0 < he; p0 += 256) {     // four loads in flight per lane
+                int32_t u[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = p0 + 64 * q < he ? idx[p0 + 64 * q] : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) hc += u[q] >= 0 && rank[u[q]] > hr;
+            }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) hc += __shfl_xor(hc, o, 64);
             if (lane == 0) outdeg[hr] = hc;
@@ -479,13 +489,22 @@ __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *idx, co
             const int64_t hb = __shfl(b, src, 64), he = hb + __shfl(len, src, 64);
             const int32_t hr = __shfl(rv, src, 64);
             int64_t hw = __shfl(w, src, 64);
-            for (int64_t q = hb; q < he; q += 64) {
-                const int64_t p = q + lane;
-                const int32_t ru = p < he ? rank[idx[p]] : -1;
-                const bool keep = ru > hr;
-                const uint64_t m = __ballot(keep);
-                if (keep) oidx[hw + __popcll(m & below)] = ru;
-                hw += __popcll(m);
+            for (int64_t q0 = hb; q0 < he; q0 += 256) {            // four loads in flight per lane
+                int32_t ru[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t p = q0 + 64 * q + lane;
+                    ru[q] = p < he ? idx[p] : -1;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ru[q] = ru[q] >= 0 ? rank[ru[q]] : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool keep = ru[q] > hr;
+                    const uint64_t m = __ballot(keep);
+                    if (keep) oidx[hw + __popcll(m & below)] = ru[q];
+                    hw += __popcll(m);
+                }
             }
         }
     }
@@ -552,33 +571,34 @@ __global__ void __launch_bounds__(256) k_row_sort_small(int64_t n, const int64_t
     if (stats && lane == 0 && dmax > 0) atomicMax((unsigned long long *)&stats[1], (unsigned long long)dmax);
 }
 
-// Rows of 65..2048 entries (the list mid[0 .. *cnt)): one block per row; each element's
-// destination is the count of smaller entries in the row, read back from LDS as broadcasts.
-__global__ void __launch_bounds__(256) k_row_sort_mid(const int32_t *mid, const int32_t *cnt, const int64_t *ooff,
-                                                      int32_t *oidx) {
-    __shared__ int32_t buf[kMidRow];
-    const int32_t nl = *cnt;
-    for (int32_t l = blockIdx.x; l < nl; l += gridDim.x) {
-        const int32_t r = mid[l];
-        const int64_t s = ooff[r];
-        const int d = (int)(ooff[r + 1] - s);
-        for (int i = threadIdx.x; i < d; i += blockDim.x) buf[i] = oidx[s + i];
-        __syncthreads();
-        for (int i = threadIdx.x; i < d; i += blockDim.x) {
-            const int32_t x = buf[i];
-            int pos = 0;
-            for (int j = 0; j < d; ++j) pos += buf[j] < x;
-            oidx[s + pos] = x;
+// Ascending bitonic sort of buf[0 .. p2) in LDS by the whole block (p2 a power of two).
+__device__ void block_bitonic(int32_t *buf, int p2) {
+    for (int size = 2; size <= p2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < (p2 >> 1); i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int32_t a = buf[lo], b = buf[hi];
+                if ((a > b) == up) {
+                    buf[lo] = b;
+                    buf[hi] = a;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
-// Rows longer than 2048 (the list rows[0 .. *cnt)): one block per row, bitonic sort in
-// LDS (padded to a power of two).
-__global__ void k_row_sort_big(const int32_t *rows, const int32_t *cnt, const int64_t *ooff, int32_t *oidx,
-                               int32_t *err) {
-    extern __shared__ int32_t big[];
+// One block per listed row (rows[0 .. *cnt)), bitonic sort in LDS padded to a power of
+// two: rows of 65..kMidRow entries in a static buffer, longer ones (up to
+// ARB_MAX_ROW_SORT) in dynamic LDS.
+template <bool BIG>
+__global__ void __launch_bounds__(256) k_row_sort_lds(const int32_t *rows, const int32_t *cnt, const int64_t *ooff,
+                                                      int32_t *oidx, int32_t *err) {
+    __shared__ int32_t mid_buf[BIG ? 1 : kMidRow];
+    extern __shared__ int32_t big_buf[];
+    int32_t *buf = BIG ? big_buf : mid_buf;
     const int32_t nl = *cnt;
     for (int32_t l = blockIdx.x; l < nl; l += gridDim.x) {
         const int32_t r = rows[l];
@@ -591,21 +611,10 @@ __global__ void k_row_sort_big(const int32_t *rows, const int32_t *cnt, const in
         const int d = (int)d64;
         int p2 = 128;
         while (p2 < d) p2 <<= 1;
-        for (int i = threadIdx.x; i < p2; i += blockDim.x) big[i] = i < d ? oidx[s + i] : 0x7fffffff;
+        for (int i = threadIdx.x; i < p2; i += blockDim.x) buf[i] = i < d ? oidx[s + i] : 0x7fffffff;
         __syncthreads();
-        for (int size = 2; size <= p2; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int i = threadIdx.x; i < (p2 >> 1); i += blockDim.x) {
-                    int lo = 2 * i - (i & (stride - 1));
-                    int hi = lo + stride;
-                    bool up = (lo & size) == 0;
-                    int32_t a = big[lo], b = big[hi];
-                    if ((a > b) == up) { big[lo] = b; big[hi] = a; }
-                }
-                __syncthreads();
-            }
-        }
-        for (int i = threadIdx.x; i < d; i += blockDim.x) oidx[s + i] = big[i];
+        block_bitonic(buf, p2);
+        for (int i = threadIdx.x; i < d; i += blockDim.x) oidx[s + i] = buf[i];
         __syncthreads();
     }
 }
@@ -871,8 +880,8 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
     int32_t *mid_rows = w.vals_alt, *big_rows = reinterpret_cast<int32_t *>(w.keys_alt), *row_cnt = w.err + 1;
     if ((rc = fill_i32(row_cnt, 0, 2, s))) return rc;
     k_row_sort_small<<<g16, 256, 0, s>>>(n, out->offsets, out->indices, stats, mid_rows, big_rows, row_cnt);
-    k_row_sort_mid<<<grid_for(n, 1, 8192), 256, 0, s>>>(mid_rows, row_cnt, out->offsets, out->indices);
-    k_row_sort_big<<<grid_for(n, 64, 256), 256, ARB_MAX_ROW_SORT * sizeof(int32_t), s>>>(
+    k_row_sort_lds<false><<<grid_for(n, 1, 8192), 256, 0, s>>>(mid_rows, row_cnt, out->offsets, out->indices, w.err);
+    k_row_sort_lds<true><<<grid_for(n, 64, 256), 256, ARB_MAX_ROW_SORT * sizeof(int32_t), s>>>(
         big_rows, row_cnt + 1, out->offsets, out->indices, w.err);
     if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     if (round_out) {
