@@ -101,10 +101,15 @@ struct TeamLds {
     using RingT = typename std::conditional<CR, uint16_t, uint32_t>::type;
     static constexpr int SPAN = TierCfg<W, PV, 1>::SPAN;
     static constexpr int SW = SPAN > 0 ? SPAN / 32 : 1;
+    // the 64-tier (always hash mode) screens its second-level entries with a member filter;
+    // in the larger tiers it measured slower (bitmap mode is as cheap, and their sets fill
+    // more of the filter)
+    static constexpr bool FILTER = W == 2;
     int32_t S[D];
     unsigned long long H[HS];
     uint32_t bm[SW];        // member bitmap over ids first .. first + SPAN - 1
     uint16_t pre[SW];       // local id of the first member in each bitmap word
+    uint32_t flt[FILTER ? 64 : 1];   // 2048-bit filter of S (bit filter_hash(s) per member s)
     alignas(16) uint32_t rows[D * RS];
     unsigned long long cnt[PV ? D : 1];
     union {
@@ -210,6 +215,12 @@ __device__ __forceinline__ int member_find(const AS3<L> *T, int32_t w, int32_t f
     }
     return hash_find(T, (uint32_t)w);
 }
+
+// Bit of vertex id w in the 2048-bit member filter: most second-level list entries are
+// not in S (on R-MAT 20, 99% in the 64-tier), and a set bit is needed for a member, so a
+// clear bit rejects an entry without a hash probe.  The filter's 64 words sit one per
+// lane and are read with a lane shuffle, which has no bank conflicts.
+__device__ __forceinline__ uint32_t filter_hash(int32_t w) { return ((uint32_t)w * 2246822519u) >> 21; }
 
 // bits of word w that stand for local ids greater than z
 __device__ __forceinline__ uint32_t gtmask(int z, int w) {
@@ -488,6 +499,7 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
                                              int32_t first, int32_t last, bool bmode, int wv, int lane,
                                              unsigned long long &mine, unsigned long long &words) {
     AS3<ListEnt> *lt = T->q.lt[wv];
+    const uint32_t fw = Lds::FILTER ? T->flt[lane] : 0u;   // this lane's word of the member filter
     const int nl = g0 < d ? (d - g0 + gstep - 1) / gstep : 0;
     for (int gb = 0; gb < nl; gb += 64) {
         const int t = gb + lane;
@@ -536,8 +548,20 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
                     r[q] = c_row;
                 }
             }
+            bool maybe[GU];
+            if (!Lds::FILTER || bmode) {
+#pragma unroll
+                for (int q = 0; q < GU; ++q) maybe[q] = true;
+            } else {
+#pragma unroll
+                for (int q = 0; q < GU; ++q) {
+                    const uint32_t h = filter_hash(w[q]);
+                    maybe[q] = (__shfl(fw, (int)(h >> 5), 64) >> (h & 31u)) & 1u;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < GU; ++q) {
+                if (!maybe[q]) continue;
                 const int j = member_find(T, w[q], first, last, bmode);
                 if (j < 0) continue;
                 const int i = r[q];
@@ -636,6 +660,8 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     } else {
         for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
     }
+    if (Lds::FILTER)
+        for (int i = tlid; i < 64; i += TT) T->flt[i] = 0u;
     if (need >= 3)
         for (int i = tlid; i < d * Lds::RS; i += TT) T->rows[i] = 0u;
     if (tlid == 0) T->next = TW;
@@ -651,6 +677,11 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     } else {
         for (int i = tlid; i < d; i += TT) hash_insert(T, (uint32_t)T->S[i], (uint32_t)i);
     }
+    if (Lds::FILTER)
+        for (int i = tlid; i < d; i += TT) {
+            const uint32_t h = filter_hash(T->S[i]);
+            lds_or(&T->flt[h >> 5], 1u << (h & 31u));
+        }
     team_sync<TW, TPB>();
 
     unsigned long long mine = 0;      // this lane's share of the item's clique count
@@ -790,9 +821,9 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
 
 // Waves per SIMD the register allocation must allow: in the two smallest tiers at depth
 // <= 2 the latency of the list reads dominates, and more resident waves hide more of it
-// (measured: 6 and 5 beat the 4 that their register use would give)
+// (measured: 5 beats the 4 that their register use would give)
 template <int W, bool PV, int LMAX> constexpr int tier_min_waves() {
-    return (PV || LMAX > 2) ? 1 : (W == 2 ? 6 : (W == 4 ? 5 : 1));
+    return (PV || LMAX > 2) ? 1 : (W == 2 || W == 4 ? 5 : 1);
 }
 
 template <int W, int LMAX, bool PV, bool INSTR>
