@@ -64,6 +64,19 @@ def test_orient_parity(arb, orc, gi, eps):
     check_orient(arb, orc, g, eps)
 
 
+def test_orient_long_rows(arb, orc):
+    # K_2100: directed rows of every length 0..2099, so every row-sort class (16-lane
+    # groups, wave, listed mid rows, listed rows above 2048) and the whole-wave walk of
+    # rows above 64 entries are compared byte for byte with the oracle
+    g = gg.complete(2100)
+    say("orient", g.name, g.n, g.m)
+    o = check_orient(arb, orc, g, 1.0)
+    assert int(o["stats"][1]) == 2099
+    t, pv = gpu_count(arb, o, 3, per_vertex=True)
+    assert t == math.comb(2100, 3)
+    assert np.all(pv == math.comb(2099, 2))
+
+
 def test_orient_hand_example(arb, orc):
     import json
     import os
