@@ -28,40 +28,46 @@ __device__ __forceinline__ void load_weights(const uint16_t *wb, float *W) {
 
 // ------------------------------------------------------------------ features
 
-// A lane per row; rows with more than 32 out-neighbours are summed by the whole wave.
+// A group of 16 lanes per row (four per wave); rows with more than 64 out-neighbours are
+// summed by the whole wave after its groups' rows, four loads in flight per lane.
 __global__ void k_feat_rows(int64_t n, const int64_t *off, const int32_t *idx, float *feat) {
-    const int lane = threadIdx.x & 63;
-    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-        const int64_t r = base + lane;
+    const int lane = threadIdx.x & 63, sl = lane & 15;
+    int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (; r - (lane >> 4) < n; r += ngrp) {          // while the wave's first group has a row
         int64_t s = 0, e = 0;
         if (r < n) {
             s = off[r];
             e = off[r + 1];
         }
-        const bool big = e - s > 32;
+        const bool big = e - s > 64;
         int64_t sum = 0;
         if (!big)
-            for (int64_t p = s; p < e; ++p) {
+            for (int64_t p = s + sl; p < e; p += 16) {
                 const int32_t u = idx[p];
                 sum += off[u + 1] - off[u];
             }
-        uint64_t m = __ballot(big);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
+        uint64_t m = __ballot(big && sl == 0);
         while (m) {
             const int src = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
             const int64_t ss = __shfl(s, src, 64), ee = __shfl(e, src, 64);
             int64_t part = 0;
-            for (int64_t p = ss + lane; p < ee; p += 64) {
-                const int32_t u = idx[p];
-                part += off[u + 1] - off[u];
+            for (int64_t p0 = ss + lane; p0 < ee; p0 += 256) {
+                int32_t u[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = p0 + 64 * q < ee ? idx[p0 + 64 * q] : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (u[q] >= 0) part += off[u[q] + 1] - off[u[q]];
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-            if (lane == src) sum = part;
+            if ((lane >> 4) == (src >> 4)) sum = part;
         }
-        if (r < n) {
+        if (r < n && sl == 0) {
             feat[3 * r + 0] = log2f(1.0f + (float)(e - s));
             feat[3 * r + 1] = log2f(1.0f + (float)sum);
         }
@@ -392,7 +398,7 @@ extern "C" int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const
     }
     const int64_t n = dg->n;
     if (n > 0) {
-        k_feat_rows<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, dg->offsets, dg->indices, feat);
+        k_feat_rows<<<grid_for(n * 16, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, feat);
         if (rank) k_feat_round<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, round_orig, rank, feat);
         else k_feat_round<<<1, 64, 0, s>>>(0, nullptr, nullptr, feat);
         if (hipGetLastError() != hipSuccess) { set_error(ARB_EHIP); return ARB_EHIP; }
