@@ -5,13 +5,14 @@
 //  * work item = a root v (candidate set S = N+(v), k-1 vertices still to choose), or,
 //    for a root split by the scheduler, a pair (v, c) with c in N+(v)
 //    (S = N+(v) ∩ N+(c), k-2 to choose) -- the paper's node vs edge parallelism;
-//  * one team (1..8 waves) per item stages S in LDS, relabelled 0..d-1 in rank order
+//  * one team (1..16 waves) per item stages S in LDS, relabelled 0..d-1 in rank order
 //    (Sec. 3.4: relabel the induced subgraph to [0, O(alpha))), with an LDS hash from
 //    vertex id to local id standing in for the paper's mark array;
 //  * the second-level intersections (the first non-trivial ones) read N+(u) for every
 //    u in S from HBM with coalesced 64-lane loads and keep the members of S: this builds
-//    G[S] as one bit row per local vertex (row x = neighbours of x in S above x; in the
-//    per-vertex mode the rows are symmetric and masked on use);
+//    G[S] as one bit row per local vertex (row x = neighbours of x in S above x for
+//    totals at k = 4; symmetric rows, masked on use, when subtrees follow the pairs or in
+//    the per-vertex mode);
 //  * deeper levels never touch HBM: every candidate set is a bitmap over local ids,
 //    I' = I AND row(x) (Alg. 1, intersect), and the last level adds popcounts instead of
 //    materialising I (base case |I|).  Pairs (x, y) of the induced subgraph are spread
