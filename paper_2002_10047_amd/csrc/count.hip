@@ -101,6 +101,9 @@ __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *l
             kk = ((uint32_t)kDeadTier << kCostBits) | kCostMax;
         } else {
             int t = tier_of(d);
+            // the learned cost is evaluated for roots above the 64-tier only (its light
+            // roots balance under any order); the 64-tier keeps the degree cost
+            const float *lc = t == 0 ? nullptr : lcost;
             if (t < 0 && (k == 3 || k == 4) && d <= dbig) {
                 t = kBigTier;                  // whole root, bit rows in global scratch
                 P = 1;
@@ -108,12 +111,12 @@ __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *l
                 t = kNumTiers - 1;
                 P = -1;
             } else {
-                P = root_parts(d, split_deg, lcost, split_cost, v);
+                P = root_parts(d, split_deg, lc, split_cost, v);
             }
             const float per = P > 0 ? (float)P : (float)d;
             // degree cost: out-degree per item; learned: predicted log2 work per item in
             // steps of 1/64
-            float c = lcost ? fmaxf(lcost[v] - log2f(per), 0.f) * 64.f : (float)d / per;
+            float c = lc ? fmaxf(lc[v] - log2f(per), 0.f) * 64.f : (float)d / per;
             uint32_t cq = (uint32_t)fminf(c, (float)kCostMax);
             kk = ((uint32_t)t << kCostBits) | (kCostMax - cq);
         }

@@ -143,7 +143,8 @@ __device__ __forceinline__ void split_bf16(const f32x4 h, bf16x4 &hi, bf16x4 &lo
 }
 
 // With off != nullptr (the schedule's use), tiles whose 16 roots all have fewer than
-// dmin out-neighbours (roots the count drops) are skipped; their y stays unset.
+// dmin out-neighbours (roots whose cost the schedule does not read) are skipped; their y
+// stays unset.
 __global__ void __launch_bounds__(256) k_mlp_fwd_mfma(const uint16_t *wb, const float *x, int64_t rows, float *y,
                                                        const int64_t *off, int64_t dmin) {
     __shared__ float W[NP];
@@ -379,8 +380,9 @@ __global__ void k_to_bf16(const float *w, uint16_t *wb, int64_t n) {
 
 int learned_cost(const arb_ocsr *dg, int k, const uint16_t *w, const float *feat, float *cost, hipStream_t s) {
     if (dg->n == 0) return ARB_OK;
-    k_mlp_fwd_mfma<<<grid_for((dg->n + 15) / 16 * 64, 256, 512), 256, 0, s>>>(w, feat, dg->n, cost, dg->offsets,
-                                                                               (int64_t)(k - 1));
+    // the schedule reads the cost of roots above the 64-tier only
+    const int64_t dmin = k - 1 > 65 ? k - 1 : 65;
+    k_mlp_fwd_mfma<<<grid_for((dg->n + 15) / 16 * 64, 256, 512), 256, 0, s>>>(w, feat, dg->n, cost, dg->offsets, dmin);
     ARB_CHECK_LAUNCH();
     return ARB_OK;
 }
