@@ -216,9 +216,9 @@ def main():
         return
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU; runs on several GPUs are not implemented",
                           "n_gpus": a.gpus}))
-        log("bench.py runs on exactly one GPU (--gpus 1); the sharded design is described in DESIGN.md")
+        log("bench.py runs on exactly one GPU (--gpus 1): the counting path is not sharded across GPUs")
         sys.exit(2)
     import numpy as np
     import torch
