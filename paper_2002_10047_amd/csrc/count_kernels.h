@@ -820,11 +820,11 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     return mine;
 }
 
-// Waves per SIMD the register allocation must allow: in the two smallest tiers at depth
-// <= 2 the latency of the list reads dominates, and more resident waves hide more of it
-// (measured: 5 beats the 4 that their register use would give)
+// Waves per SIMD the register allocation must allow: in the two smallest tiers the
+// latency of the list reads dominates, and more resident waves hide more of it (measured:
+// 5 beats the 3-4 that their register use would give, at every depth; 6 is slower)
 template <int W, bool PV, int LMAX> constexpr int tier_min_waves() {
-    return (PV || LMAX > 2) ? 1 : (W == 2 || W == 4 ? 5 : 1);
+    return PV ? 1 : (W == 2 || W == 4 ? 5 : 1);
 }
 
 template <int W, int LMAX, bool PV, bool INSTR>
