@@ -6,8 +6,9 @@ edge present, no self-loops, no duplicates).  It holds none of the clique-counti
 or orientation arithmetic, so neither the HIP path nor the CPU oracle depends on the
 other through it.
 
-All randomness comes from numpy's PCG64 generator seeded explicitly; the same seed
-and numpy version give the same graph byte for byte.
+Randomness comes from numpy's PCG64 generator seeded explicitly (the same seed and
+numpy version give the same graph byte for byte), or, for the counter-based families,
+from SplitMix64 evaluated at each draw's index on either side.
 
 Workload families (the shapes the paper's experiments use are social/web graphs of
 Table 1; these synthetic families stand in for them):
@@ -16,6 +17,8 @@ Table 1; these synthetic families stand in for them):
 * ``rmat``         recursive-matrix (R-MAT) power-law graph
 * ``chung_lu``     Chung-Lu expected-degree power-law graph with planted dense communities
 * ``rgg``          random geometric graph on the unit torus (2-D or 3-D)
+* ``rmat_cb_*``, ``rgg_cb_*``  R-MAT and 3-D RGG from a counter-based stream, built
+                   identically on the GPU (torch) and on the host (numpy)
 * ``batch_mix``    a batch of graphs of uneven size mixing G(n,p), R-MAT and 2-D RGG
 * small exact families: complete, Turan, cycle, star, empty, G(n,p)
 """
@@ -192,38 +195,249 @@ def rmat(scale: int, nsamples: int, a: float = 0.57, b: float = 0.19, c: float =
     return csr_from_pairs(n, u, v, f"rmat(scale={scale},samples={nsamples},seed={seed})")
 
 
-def rmat_device(scale: int, nsamples: int, a: float = 0.57, b: float = 0.19, c: float = 0.19, seed: int = 51,
-                device="cuda", chunk: int = 1 << 24):
-    """R-MAT as in rmat(), generated on the GPU with torch's seeded device generator (for
-    graphs too large to build on the host in test time): (n, offsets int64[n+1], indices
-    int32[2m]) as device tensors, rows sorted, simple and symmetric.  The random stream
-    is torch's, so the graph differs from rmat() with the same seed."""
+# ---------------------------------------------------------------- counter-based generators
+#
+# The two largest workloads are generated on the GPU (seconds) and, identically, on the
+# host (minutes; for oracle totals).  Both draw from SplitMix64 (Steele, Lea and Flood,
+# "Fast splittable pseudorandom number generators", OOPSLA 2014), whose i-th output for
+# seed s is mix(s + (i + 1) * GAMMA): every draw is a function of its index alone, so the
+# two sides agree draw for draw and chunks can be generated in any order.  A uniform
+# double is the top 53 bits times 2^-53 (exact on both sides), and every comparison that
+# decides an edge is the same IEEE operations on both sides.
+
+_M64 = (1 << 64) - 1
+_SM_GAMMA = 0x9E3779B97F4A7C15
+_SM_M1 = 0xBF58476D1CE4E5B9
+_SM_M2 = 0x94D049BB133111EB
+_STREAM_RMAT, _STREAM_PERM, _STREAM_RGG = 1, 2, 3
+
+
+def _mix_int(z: int) -> int:
+    z &= _M64
+    z = ((z ^ (z >> 30)) * _SM_M1) & _M64
+    z = ((z ^ (z >> 27)) * _SM_M2) & _M64
+    return z ^ (z >> 31)
+
+
+def stream_key(seed: int, stream: int) -> int:
+    """64-bit key of one stream of draws of a seeded workload."""
+    return _mix_int((_mix_int(int(seed)) + int(stream) * _SM_GAMMA) & _M64)
+
+
+def _signed(x: int) -> int:
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def sm64_np(key: int, i) -> np.ndarray:
+    """uint64 SplitMix64 output number i (integer array) of the generator keyed `key`."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(key) + (np.asarray(i).astype(np.uint64) + np.uint64(1)) * np.uint64(_SM_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_SM_M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_SM_M2)
+    return z ^ (z >> np.uint64(31))
+
+
+def _srl_t(z, s: int):
+    """logical right shift of an int64 tensor holding uint64 bits"""
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def sm64_torch(key: int, i):
+    """sm64_np on an int64 tensor of indices (any device): int64 tensor of the uint64 bits
+    (two's-complement wrap-around of int64 addition and multiplication)."""
+    z = (i + 1) * _signed(_SM_GAMMA) + _signed(key)
+    z = (z ^ _srl_t(z, 30)) * _signed(_SM_M1)
+    z = (z ^ _srl_t(z, 27)) * _signed(_SM_M2)
+    return z ^ _srl_t(z, 31)
+
+
+def unif_np(key: int, i) -> np.ndarray:
+    return (sm64_np(key, i) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def unif_torch(key: int, i):
     import torch
-    gen = torch.Generator(device=device)
-    gen.manual_seed(seed)
+    return _srl_t(sm64_torch(key, i), 11).to(torch.float64) * (2.0 ** -53)
+
+
+def rmat_cb_permutation_np(scale: int, seed: int) -> np.ndarray:
+    """The vertex relabelling of the counter-based R-MAT: ids sorted (stably) by a 63-bit
+    draw each; vertex u becomes perm[u]."""
     n = 1 << scale
-    perm = torch.randperm(n, generator=gen, device=device)
+    keys = (sm64_np(stream_key(seed, _STREAM_PERM), np.arange(n, dtype=np.int64)) >> np.uint64(1)).astype(np.int64)
+    return np.argsort(keys, kind="stable").astype(np.int64)
+
+
+def rmat_cb_host(scale: int, nsamples: int, a: float = 0.57, b: float = 0.19, c: float = 0.19, seed: int = 51,
+                 chunk: int = 1 << 22) -> "Graph":
+    """R-MAT (as rmat()) from the counter-based stream: sample i at level l uses draw
+    i * scale + l; ids relabelled by rmat_cb_permutation_np; self-loops and duplicates
+    dropped.  Byte-identical to rmat_cb_device(scale, nsamples, seed=seed)."""
+    kr = stream_key(seed, _STREAM_RMAT)
+    perm = rmat_cb_permutation_np(scale, seed)
+    ab, abc = a + b, a + b + c
     keys = []
-    left = nsamples
-    while left > 0:
-        cnt = min(chunk, left)
-        left -= cnt
+    for i0 in range(0, nsamples, chunk):
+        cnt = min(chunk, nsamples - i0)
+        i = np.arange(i0, i0 + cnt, dtype=np.int64) * scale
+        u = np.zeros(cnt, dtype=np.int64)
+        v = np.zeros(cnt, dtype=np.int64)
+        for lvl in range(scale):
+            r = unif_np(kr, i + lvl)
+            bit = np.int64(1) << np.int64(scale - 1 - lvl)
+            u |= (r >= ab).astype(np.int64) * bit
+            v |= (((r >= a) & (r < ab)) | (r >= abc)).astype(np.int64) * bit
+        u, v = perm[u], perm[v]
+        keep = u != v
+        u, v = u[keep], v[keep]
+        keys.append(np.unique((np.minimum(u, v) << scale) | np.maximum(u, v)))
+    key = np.unique(np.concatenate(keys)) if keys else np.empty(0, np.int64)
+    del keys
+    off, idx = host_csr_from_keys(key, scale, 1 << scale)
+    return Graph(1 << scale, off, idx, f"rmat_cb(scale={scale},samples={nsamples},seed={seed})")
+
+
+def rmat_cb_device(scale: int, nsamples: int, a: float = 0.57, b: float = 0.19, c: float = 0.19, seed: int = 51,
+                   device="cuda", chunk: int = 1 << 24):
+    """rmat_cb_host generated on the GPU with torch elementwise operations: (n, offsets
+    int64[n+1], indices int32[2m]) device tensors, byte-identical to the host graph."""
+    import torch
+    n = 1 << scale
+    kr = stream_key(seed, _STREAM_RMAT)
+    pk = _srl_t(sm64_torch(stream_key(seed, _STREAM_PERM), torch.arange(n, dtype=torch.int64, device=device)), 1)
+    perm = torch.sort(pk, stable=True).indices
+    del pk
+    ab, abc = a + b, a + b + c
+    keys = []
+    for i0 in range(0, nsamples, chunk):
+        cnt = min(chunk, nsamples - i0)
+        i = torch.arange(i0, i0 + cnt, dtype=torch.int64, device=device) * scale
         u = torch.zeros(cnt, dtype=torch.int64, device=device)
         v = torch.zeros(cnt, dtype=torch.int64, device=device)
         for lvl in range(scale):
-            r = torch.rand(cnt, generator=gen, device=device, dtype=torch.float64)
+            r = unif_torch(kr, i + lvl)
             bit = 1 << (scale - 1 - lvl)
-            u |= (r >= a + b).to(torch.int64) * bit
-            v |= (((r >= a) & (r < a + b)) | (r >= a + b + c)).to(torch.int64) * bit
+            u |= (r >= ab).to(torch.int64) * bit
+            v |= (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64) * bit
+        del i, r
         u = perm[u]
         v = perm[v]
         keep = u != v
         u, v = u[keep], v[keep]
-        keys.append((torch.minimum(u, v) << scale) | torch.maximum(u, v))
+        keys.append(torch.unique((torch.minimum(u, v) << scale) | torch.maximum(u, v)))
         del u, v, keep
     key = torch.unique(torch.cat(keys))           # sorted, one entry per undirected edge
     del keys
     off, idx = _device_csr_from_keys(key, scale, n)
+    return n, off, idx
+
+
+def host_csr_from_keys(key: np.ndarray, bits: int, n: int):
+    """numpy counterpart of _device_csr_from_keys: sorted unique keys lo << bits | hi
+    (lo < hi) -> (offsets int64[n+1], indices int32[2m]), rows ascending."""
+    key = np.asarray(key, np.int64)
+    m = key.shape[0]
+    mask = (1 << bits) - 1
+    lo = key >> bits
+    hi = key & mask
+    deg_up = np.bincount(lo, minlength=n).astype(np.int64)
+    deg_dn = np.bincount(hi, minlength=n).astype(np.int64)
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(deg_up + deg_dn, out=off[1:])
+    idx = np.empty(2 * m, dtype=np.int32)
+    first_up = np.cumsum(deg_up) - deg_up
+    idx[off[lo] + deg_dn[lo] + (np.arange(m, dtype=np.int64) - first_up[lo])] = hi.astype(np.int32)
+    del first_up
+    k2 = np.sort((hi << bits) | lo)
+    del lo, hi
+    hi2 = k2 >> bits
+    lo2 = k2 & mask
+    del k2
+    first_dn = np.cumsum(deg_dn) - deg_dn
+    idx[off[hi2] + (np.arange(m, dtype=np.int64) - first_dn[hi2])] = lo2.astype(np.int32)
+    return off, idx
+
+
+def _rgg_radius(n: int, avg_deg: float) -> float:
+    return (avg_deg / ((4.0 / 3.0) * math.pi * n)) ** (1.0 / 3.0)
+
+
+def rgg_cb_host(n: int, avg_deg: float = 40.0, seed: int = 52) -> "Graph":
+    """3-D random geometric graph on the unit torus from the counter-based stream (point
+    i's coordinate j is draw 3 i + j): an edge iff dx*dx + dy*dy + dz*dz <= r*r, with
+    d = min(|a - b|, 1 - |a - b|) per axis, summed left to right, and
+    r = (avg_deg / (4/3 pi n))^(1/3).  Candidate pairs come from a k-d tree at a slightly
+    larger radius and are decided by that expression, so the graph is byte-identical to
+    rgg_cb_device(n, avg_deg, seed)."""
+    from scipy.spatial import cKDTree
+    pts = unif_np(stream_key(seed, _STREAM_RGG), np.arange(3 * n, dtype=np.int64)).reshape(n, 3)
+    r = _rgg_radius(n, avg_deg)
+    tree = cKDTree(pts, boxsize=1.0)
+    pairs = tree.query_pairs(r * (1.0 + 1e-9), output_type="ndarray")
+    del tree
+    keep = np.zeros(pairs.shape[0], bool)
+    step = 1 << 24
+    for s0 in range(0, pairs.shape[0], step):
+        a = pts[pairs[s0:s0 + step, 0]]
+        b = pts[pairs[s0:s0 + step, 1]]
+        dv = np.abs(a - b)
+        dv = np.minimum(dv, 1.0 - dv)
+        d2 = dv[:, 0] * dv[:, 0] + dv[:, 1] * dv[:, 1] + dv[:, 2] * dv[:, 2]
+        keep[s0:s0 + step] = d2 <= r * r
+    pairs = pairs[keep]
+    bits = max(1, (n - 1).bit_length())
+    lo = np.minimum(pairs[:, 0], pairs[:, 1]).astype(np.int64)
+    hi = np.maximum(pairs[:, 0], pairs[:, 1]).astype(np.int64)
+    del pairs
+    key = np.unique((lo << bits) | hi)
+    del lo, hi
+    off, idx = host_csr_from_keys(key, bits, n)
+    return Graph(n, off, idx, f"rgg_cb(n={n},dim=3,deg={avg_deg},seed={seed})")
+
+
+def rgg_cb_device(n: int, avg_deg: float = 40.0, seed: int = 52, device="cuda", chunk: int = 1 << 21):
+    """rgg_cb_host built on the GPU with a cell list (cells of side >= r; the 27 cells
+    around each point's cell are searched): (n, offsets int64[n+1], indices int32[2m])
+    device tensors, byte-identical to the host graph."""
+    import torch
+    r = _rgg_radius(n, avg_deg)
+    G = max(3, int(math.floor(1.0 / r)))            # cells per axis, side 1/G >= r
+    pts = unif_torch(stream_key(seed, _STREAM_RGG), torch.arange(3 * n, dtype=torch.int64, device=device)).view(n, 3)
+    cxyz = torch.clamp((pts * G).to(torch.int64), max=G - 1)
+    cell = (cxyz[:, 0] * G + cxyz[:, 1]) * G + cxyz[:, 2]
+    cell_sorted, order = torch.sort(cell)
+    ncell = G * G * G
+    cstart = torch.zeros(ncell + 1, dtype=torch.int64, device=device)
+    cstart[1:] = torch.cumsum(torch.bincount(cell_sorted, minlength=ncell), 0)
+    kmax = int((cstart[1:] - cstart[:-1]).max())
+    bits = max(1, (n - 1).bit_length())
+    r2 = r * r
+    keys = []
+    for c0 in range(0, n, chunk):
+        ids = order[c0:c0 + chunk]                  # points of this chunk, in cell order
+        cx, cy, cz = cxyz[ids, 0], cxyz[ids, 1], cxyz[ids, 2]
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    nc = (((cx + dx) % G) * G + (cy + dy) % G) * G + (cz + dz) % G
+                    s0 = cstart[nc]
+                    cnt = cstart[nc + 1] - s0
+                    for t in range(kmax):
+                        ok = cnt > t
+                        if not bool(ok.any()):
+                            break
+                        src = ids[ok]
+                        dst = order[s0[ok] + t]
+                        keep = src < dst
+                        src, dst = src[keep], dst[keep]
+                        dv = torch.abs(pts[src] - pts[dst])
+                        dv = torch.minimum(dv, 1.0 - dv)
+                        d2 = dv[:, 0] * dv[:, 0] + dv[:, 1] * dv[:, 1] + dv[:, 2] * dv[:, 2]
+                        close = d2 <= r2
+                        keys.append((src[close] << bits) | dst[close])
+    key = torch.unique(torch.cat(keys))
+    del keys
+    off, idx = _device_csr_from_keys(key, bits, n)
     return n, off, idx
 
 
@@ -253,57 +467,6 @@ def _device_csr_from_keys(key, bits: int, n: int):
     first_dn = torch.cumsum(deg_dn, 0) - deg_dn
     idx[off[hi2] + (torch.arange(m, device=device) - first_dn[hi2])] = lo2.to(torch.int32)
     return off, idx
-
-
-def rgg_device(n: int, avg_deg: float = 40.0, seed: int = 52, device="cuda", chunk: int = 1 << 21):
-    """3-D random geometric graph as in rgg(n, 3, avg_deg): n uniform points on the unit
-    torus [0,1)^3, an edge iff the torus distance is at most r = (avg_deg / (4/3 pi n))^(1/3),
-    built on the GPU with a cell list (cells of side >= r, the 27 neighbouring cells of each
-    point's cell searched); torch's seeded device generator, so the graph differs from
-    rgg() with the same seed.  Returns (n, offsets int64[n+1], indices int32[2m])."""
-    import torch
-    gen = torch.Generator(device=device)
-    gen.manual_seed(seed)
-    r = (avg_deg / ((4.0 / 3.0) * math.pi * n)) ** (1.0 / 3.0)
-    G = max(3, int(math.floor(1.0 / r)))            # cells per axis, side 1/G >= r
-    pts = torch.rand((n, 3), generator=gen, device=device, dtype=torch.float64)
-    cxyz = torch.clamp((pts * G).to(torch.int64), max=G - 1)
-    cell = (cxyz[:, 0] * G + cxyz[:, 1]) * G + cxyz[:, 2]
-    cell_sorted, order = torch.sort(cell)
-    ncell = G * G * G
-    cstart = torch.zeros(ncell + 1, dtype=torch.int64, device=device)
-    cstart[1:] = torch.cumsum(torch.bincount(cell_sorted, minlength=ncell), 0)
-    kmax = int((cstart[1:] - cstart[:-1]).max())
-    bits = max(1, (n - 1).bit_length())
-    r2 = r * r
-    keys = []
-    for c0 in range(0, n, chunk):
-        ids = order[c0:c0 + chunk]                  # points of this chunk, in cell order
-        p = pts[ids]
-        cx, cy, cz = cxyz[ids, 0], cxyz[ids, 1], cxyz[ids, 2]
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    nc = (((cx + dx) % G) * G + (cy + dy) % G) * G + (cz + dz) % G
-                    s0 = cstart[nc]
-                    cnt = cstart[nc + 1] - s0
-                    for t in range(kmax):
-                        ok = cnt > t
-                        if not bool(ok.any()):
-                            break
-                        src = ids[ok]
-                        dst = order[s0[ok] + t]
-                        keep = src < dst
-                        src, dst = src[keep], dst[keep]
-                        dv = torch.abs(pts[src] - pts[dst])
-                        dv = torch.minimum(dv, 1.0 - dv)
-                        close = (dv * dv).sum(1) <= r2
-                        keys.append((src[close] << bits) | dst[close])
-        del p
-    key = torch.unique(torch.cat(keys))
-    del keys
-    off, idx = _device_csr_from_keys(key, bits, n)
-    return n, off, idx
 
 
 def _capped_weights(n: int, beta: float, total: float, wmax: float) -> np.ndarray:

@@ -16,9 +16,18 @@ def arb():
     return arb
 
 
+def _k4_iso(z):
+    # K_4 plus z isolated vertices: with z = 4, k = 3, eps = 1 every K_4 vertex sits exactly
+    # at the removal threshold (Sec. 4.2's "at most")
+    u = [a for a in range(4) for b in range(a + 1, 4)]
+    v = [b for a in range(4) for b in range(a + 1, 4)]
+    return gg.csr_from_pairs(4 + z, np.array(u), np.array(v))
+
+
 @pytest.mark.parametrize("name,mk", [("c1", lambda: gg.config_graph("c1")), ("gnp", lambda: gg.gnp(600, 0.05, 4)),
                                      ("rmat13", lambda: gg.rmat(13, 100000, seed=4)),
-                                     ("K30", lambda: gg.complete(30)), ("empty", lambda: gg.empty(4))])
+                                     ("K30", lambda: gg.complete(30)), ("empty", lambda: gg.empty(4)),
+                                     ("K4+4", lambda: _k4_iso(4)), ("K4+5", lambda: _k4_iso(5))])
 def test_approx_peel_parity(arb, orc, name, mk):
     g = mk()
     off, idx = arb.to_device_csr(g)

@@ -447,6 +447,28 @@ def test_approx_peel_closed_form_and_guarantee(orc):
                 assert orc.count(h, k) / mask.sum() == d
 
 
+def k4_with_isolated(z):
+    """K_4 on vertices 0..3 plus z isolated vertices."""
+    u = [a for a in range(4) for b in range(a + 1, 4)]
+    v = [b for a in range(4) for b in range(a + 1, 4)]
+    return gg.csr_from_pairs(4 + z, np.array(u), np.array(v))
+
+
+def test_approx_peel_threshold_tie(orc):
+    # Sec. 4.2 removes the vertices with AT MOST k(1+eps) times the density cliques.  K_4
+    # plus 4 isolated vertices at k = 3, eps = 1: density 4/8, threshold 3 * 2 * 4 / 8 = 3,
+    # exactly the count of every K_4 vertex.  "At most" removes all 8 in one round (best
+    # density 1/2); a strict "<" would keep the K_4 for a second round at density 1.
+    d, r, mask = orc.approx_peel(k4_with_isolated(4), 3, 1.0)
+    assert (d, r) == (0.5, 1) and mask.all()
+    # one isolated vertex fewer: threshold 24/7 > 3, the same single round either way
+    d, r, mask = orc.approx_peel(k4_with_isolated(3), 3, 1.0)
+    assert (d, r) == (4 / 7, 1)
+    # five more: threshold 24/9 < 3 keeps the K_4 (density 1 in round 2)
+    d, r, mask = orc.approx_peel(k4_with_isolated(5), 3, 1.0)
+    assert (d, r) == (1.0, 2) and mask.tolist() == [True] * 4 + [False] * 5
+
+
 def test_peel_closed_forms_and_guarantee(orc):
     # K_n: all counts equal, one round, density C(n,k)/n
     for n, k in ((10, 3), (8, 4)):
