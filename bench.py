@@ -1,13 +1,18 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the arb-count hot path on one MI355X.
 
-Workload: R-MAT scale 20 (2^20 vertices, 2^24 edge samples, a,b,c,d = .57,.19,.19,.05,
-seeded permutation, self-loops and duplicates removed), k = 3, 4, 5.
+Headline workload (the largest single-GPU configuration): the 3-D random geometric graph
+on the unit torus, 2^24 vertices, mean degree 40 (~335M edges, counter-based stream, seed
+52, built on the GPU), k = 5, 6, 7 with per-vertex counts.  One step = the whole hot path
+on the resident graph: arb_orient (eps = 1), the scheduling features, and arb_count for
+k = 5, 6 and 7 with per-vertex counts (exact totals).  `value` = k-cliques counted per
+second of step time (sum over the three k).
 
-One step = the whole hot path on the resident graph: arb_orient (eps = 1) followed by
-arb_count for k = 3, 4 and 5 (exact totals).  `value` = k-cliques counted per second of
-step time (sum over the three k).  The JSON line also carries oriented edges/s, per-k
-rates, the roofline of the dominant counting kernel and the CPU-oracle baseline.
+Also reported: R-MAT scale 26 (2^30 samples, seed 51, ~1.05 billion edges) at k = 4 and
+R-MAT scale 20 (2^24 samples, seed 2) at k = 3, 4, 5 -- orientation and count times per
+schedule (learned, degree, plain), each count checked equal across schedules -- the
+roofline of the headline's dominant counting kernel, the CPU-oracle baseline and the
+studies of the paper's other rows (sparsification, orderings, approximate peeling).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -15,7 +20,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,6 +33,9 @@ PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # LDS: 128 B/clk/CU (the CDNA3 figure) x 256 CUs x 2.4 GHz; the probe's measurement is
 # used when larger
 SPEC_LDS_GBS = 128 * 256 * 2.4e9 / 1e9
+TIER_W = [2, 4, 8, 12, 16, 24]
+TIER_CAP = [64, 128, 256, 384, 512, 768]
+CPU_THREADS = 16                      # the host-core share of one GPU on the benchmark boxes
 
 
 def log(*a):
@@ -38,43 +45,65 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--ks", default="3,4,5")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--eps", type=float, default=1.0)
-    ap.add_argument("--schedule", default="learned", choices=["plain", "persistent", "degree", "learned"])
+    ap.add_argument("--schedule", default="learned", choices=["plain", "degree", "learned"])
     ap.add_argument("--no-tune", action="store_true", help="library default options, no autotuning")
     ap.add_argument("--retune", action="store_true", help="run the autotuner even if options are cached")
     ap.add_argument("--tune-cache", default="", help="tuned-options cache file (default: the package's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="only the timed steps (profiling runs)")
-    ap.add_argument("--no-studies", action="store_true",
-                    help="skip the studies after the roofline (sparsification, orderings, peeling), so that a "
-                         "kernel trace of the run holds only the launches the roofline averages")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline's timed steps (profiling runs): no other schedule, workload or study")
+    ap.add_argument("--no-studies", action="store_true", help="skip the studies of the other rows")
+    ap.add_argument("--no-rmat26", action="store_true", help="skip the R-MAT scale-26 workload")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (counter calibration)")
     return ap.parse_args()
 
 
+# ---------------------------------------------------------------------- helpers
+
+def golden(name):
+    p = os.path.join(ROOT, "tests", "golden", "fullsize_totals.json")
+    try:
+        with open(p) as f:
+            return json.load(f).get(name)
+    except OSError:
+        return None
+
+
+def tier_of_fill(d, fill):
+    """numpy counterpart of the scheduler's tier rule: the first tier whose capacity times
+    fill/100 holds d (the largest if none), 6 above the LDS tiers."""
+    import numpy as np
+    cap = np.array(TIER_CAP)
+    t0 = np.searchsorted(cap, d, side="left")       # smallest tier that fits
+    t = np.full(d.shape, len(cap) - 1)
+    for i in range(len(cap) - 1, -1, -1):
+        t = np.where((i >= t0) & (d * 100 <= cap[i] * fill), i, t)
+    return np.where(t0 >= len(cap), len(cap), t)
+
+
 def algorithmic_units(arb, o, ks, np):
     """Per-root algorithmic units from the instrumented count: gather words and the
-    numbers c_j(v) of j-cliques inside G[N+(v)] (j <= k-2)."""
+    numbers of search-tree nodes (c_j(v), j-cliques inside G[N+(v)], summed over j <= k-2)."""
     import torch
     ooff = o["ooff"].cpu().numpy()
     oidx = o["oidx"].cpu().numpy()
     n = len(ooff) - 1
     d = np.diff(ooff)
-    rows = np.repeat(np.arange(n), d)
-    gather = np.bincount(rows, weights=d[oidx].astype(np.float64), minlength=n).astype(np.int64)
+    gather = np.zeros(n, np.int64)
+    np.add.at(gather, np.repeat(np.arange(n), d), d[oidx])
     W = (d + 31) // 32
     nodes = {}
     for k in sorted(set(ks) | {k - 1 for k in ks if k >= 4} | {3}):
         work = torch.empty(n, dtype=torch.int64, device="cuda")
-        total = torch.empty(1, dtype=torch.int64, device="cuda")
-        arb.arb_count_async(o["ooff"], o["oidx"], k, total=total, work=work)
+        arb.arb_count_async(o["ooff"], o["oidx"], k, work=work)
         torch.cuda.synchronize()
         wk = work.cpu().numpy()
+        del work
         live = d >= k - 1
         nd = np.zeros(n, np.int64)
         nd[live] = (wk[live] - gather[live]) // W[live]
@@ -82,59 +111,96 @@ def algorithmic_units(arb, o, ks, np):
     return d, W, gather, nodes
 
 
-def cpu_child(path, k, budget, cores):
-    """Child process: time the CPU oracle on a strided sample of roots (its degree order,
-    positions p with p % stride == stride // 2), shrinking the stride until the sample
-    takes about `budget` seconds.  Prints one JSON line."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_child(path, k, budget, threads):
+    """Child process: the CPU oracle (Chiba-Nishizeki, OpenMP over roots) on every
+    stride-th root of its degree order, the stride shrinking until a run takes about
+    `budget` seconds; also the oracle's setup alone (a stride of n: one root).  Prints one
+    JSON line per run."""
     import numpy as np
     import oracle
     from paper_2002_10047_amd import graphgen as gg
     z = np.load(path)
     g = gg.Graph(int(z["n"]), z["offsets"], z["indices"])
-    stride = 1 << 16
+    t1 = time.time()
+    oracle.count(g, k, nthreads=threads, stride=g.n, phase=0)
+    setup = time.time() - t1
+    stride = 1 << 14
     while True:
         t1 = time.time()
-        c = oracle.count(g, k, nthreads=cores, stride=stride, phase=stride // 2)
+        c = oracle.count(g, k, nthreads=threads, stride=stride, phase=stride // 2)
         dt = time.time() - t1
-        print(json.dumps({"k": k, "stride": stride, "count": c, "seconds": dt}), flush=True)
-        if dt >= budget / 4 or stride == 1:
+        print(json.dumps({"k": k, "stride": stride, "count": c, "seconds": dt, "setup": setup,
+                          "threads": threads}), flush=True)
+        if dt - setup >= budget / 3 or stride == 1:
             break
         stride = max(1, stride // 4)
 
 
-def cpu_baseline(g, ks, seconds):
+def cpu_run(path, k, budget, threads):
     import subprocess
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", path, str(k), str(budget),
+                            str(threads)], capture_output=True, text=True, timeout=max(60.0, 8 * budget))
+        lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    except subprocess.TimeoutExpired as e:
+        lines = [l for l in (e.stdout or b"").decode().splitlines() if l.startswith("{")]
+    return json.loads(lines[-1]) if lines else None
+
+
+def cpu_baseline(n, off_h, idx_h, ks, seconds, exact):
+    """The CPU oracle on the headline graph: per k, a strided root sample of its degree
+    order on CPU_THREADS host threads, projected to the whole graph (count x stride; time
+    = setup + (run - setup) x stride); the projected count is compared with the oracle's
+    stored whole-graph total.  Plus one single-thread run (the oracle's authority build)
+    at k = 3."""
     import tempfile
     import numpy as np
-    cores = min(16, os.cpu_count() or 1)
-    budget = seconds / len(ks)
+    budget = seconds / (len(ks) + 1)
+    out = {"unit": "k-cliques/s", "cores": CPU_THREADS, "kind": "oracle", "nproc": os.cpu_count(),
+           "cpu_model": cpu_model(), "per_k": {}}
     with tempfile.TemporaryDirectory() as td:
         path = os.path.join(td, "g.npz")
-        np.savez(path, n=g.n, offsets=g.offsets, indices=g.indices)
-        samp, cnt_x, t_x = [], 0.0, 0.0
+        np.savez(path, n=n, offsets=off_h, indices=idx_h)
+        cnt_x = t_x = 0.0
         for k in ks:
-            last = None
-            try:
-                r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", path, str(k),
-                                    str(budget), str(cores)], capture_output=True, text=True,
-                                   timeout=max(30.0, 6 * budget))
-                lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
-                last = json.loads(lines[-1]) if lines else None
-            except subprocess.TimeoutExpired as e:
-                lines = [l for l in (e.stdout or b"").decode().splitlines() if l.startswith("{")]
-                last = json.loads(lines[-1]) if lines else None
-            if not last or last["seconds"] <= 0:
+            r = cpu_run(path, k, budget, CPU_THREADS)
+            if not r or r["seconds"] <= 0:
                 continue
-            cnt_x += last["count"] * last["stride"]
-            t_x += last["seconds"] * last["stride"]
-            samp.append(f"k={k}: roots at positions p % {last['stride']} == {last['stride'] // 2} of the oracle's "
-                        f"degree order, {last['count']} cliques in {last['seconds']:.2f}s")
-            log(f"cpu oracle {samp[-1]}")
+            proj_t = r["setup"] + max(r["seconds"] - r["setup"], 0.0) * r["stride"]
+            proj_c = r["count"] * r["stride"]
+            e = {"stride": r["stride"], "sample_count": r["count"], "seconds": r["seconds"], "setup_s": r["setup"],
+                 "projected_count": proj_c, "projected_s": proj_t, "cliques_per_s": proj_c / proj_t}
+            if exact and str(k) in exact:
+                e["projected_over_exact"] = proj_c / exact[str(k)]
+            out["per_k"][str(k)] = e
+            cnt_x += proj_c
+            t_x += proj_t
+            log(f"cpu oracle k={k}: {e}")
+        r = cpu_run(path, 3, budget, 1)
+        if r:
+            proj_t = r["setup"] + max(r["seconds"] - r["setup"], 0.0) * r["stride"]
+            out["single_thread_k3"] = {"stride": r["stride"], "sample_count": r["count"], "seconds": r["seconds"],
+                                       "projected_count": r["count"] * r["stride"], "projected_s": proj_t,
+                                       "cliques_per_s": r["count"] * r["stride"] / proj_t}
     if t_x <= 0:
         return None
-    return {"value": cnt_x / t_x, "unit": "k-cliques/s", "cores": cores, "kind": "oracle",
-            "sample": "Chiba-Nishizeki oracle (OpenMP over roots) on the same graph; per k a strided root "
-                      "sample scaled by its stride, rate = sum(count*stride)/sum(seconds*stride); " + "; ".join(samp)}
+    out["value"] = cnt_x / t_x
+    out["sample"] = (f"Chiba-Nishizeki oracle (OpenMP over roots, {CPU_THREADS} threads) on the headline graph; per k "
+                     "the roots at positions p % stride == stride/2 of its degree order, projected to all roots "
+                     "(count x stride, setup + (time - setup) x stride); value = sum of projected counts / sum of "
+                     "projected times over k; projected_over_exact compares with the oracle's whole-graph total")
+    return out
 
 
 def copy_calibration(a, torch):
@@ -184,30 +250,200 @@ def measure_peaks(torch):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("count_kernels.h", "count.hip"):
+    for f in ("count_kernels.h", "count.hip", "count_big.hip"):
         with open(os.path.join(ROOT, "paper_2002_10047_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary,
+    if it was taken on the current kernel sources; else None."""
     p = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         t = json.load(f)
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
         return None
     e = t.get("kernels", {}).get(kernel)
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
-def tier_of(d):
-    import numpy as np
-    b = np.array([64, 128, 256, 384, 512, 768])
-    return np.searchsorted(b, d, side="left")
+def kernel_symbol(tier, k, pv):
+    if tier >= len(TIER_W):
+        return f"k_count_big<{int(pv)},0>"
+    return f"k_count<{TIER_W[tier]},{max(1, min(k - 3, 8))},{int(pv)},0>"
+
+
+def roofline(arb, np, torch, o, ks, pv, opts_of_k, prof, workload):
+    """Per counting kernel of the timed steps: launches, time, algorithmic HBM bytes, VALU
+    ops and LDS bytes (per-root formulas summed over the roots the kernel processed).  The
+    dominant kernel is the one with the largest total time over the timed steps."""
+    d, W, gather, nodes = algorithmic_units(arb, o, ks, np)
+    per_sym = {}
+    phase = {}
+    for e in prof:
+        k, ti = e["k"], e["tier"]
+        op = opts_of_k[k]
+        live = d >= k - 1
+        td = tier_of_fill(d, op.tier_fill)
+        sel = live & (td == ti)
+        hbm = float(4 * (d[sel] + 4 * d[sel] + gather[sel]).sum() + 16 * sel.sum())
+        if pv:
+            hbm += float(8 * (d[sel] + 1).sum())           # one u64 update per member and root
+        alu = lds = 0.0
+        if k >= 4:
+            ck2 = nodes[k][sel] - nodes[k - 1][sel]          # c_{k-2}(v)
+            deep = nodes[k][sel] - d[sel]                    # sum_{j=2}^{k-2} c_j(v)
+            # every node of depth >= 2 ANDs W words; nodes of depth k-2 also popcount them
+            alu = float((W[sel] * (deep + ck2)).sum())
+            # rows built (d), a row read and a set written per internal node (depth 1..k-3),
+            # a row read per node of depth k-2
+            lds = float((4 * W[sel] * (d[sel] + nodes[k - 1][sel] + nodes[k][sel])).sum())
+        sym = kernel_symbol(ti, k, pv)
+        s_ = per_sym.setdefault(sym, dict(launches=0, ms=0.0, hbm=0.0, alu=0.0, lds=0.0, parts=[]))
+        s_["launches"] += e["launches"]
+        s_["ms"] += e["total_ms"]
+        s_["hbm"] += e["launches"] * hbm
+        s_["alu"] += e["launches"] * alu
+        s_["lds"] += e["launches"] * lds
+        ph = phase.setdefault(k, dict(alu=0.0, lds=0.0, hbm=0.0))
+        ph["alu"] += alu
+        ph["lds"] += lds
+        ph["hbm"] += hbm
+        s_["parts"].append(f"k={k}: {e['launches']} launches, {e['total_ms'] / e['launches']:.3f} ms avg")
+    peaks = measure_peaks(torch)
+    peak_lds = max(SPEC_LDS_GBS, peaks["lds_read_GBs"] or 0.0)
+    log(f"probes: LDS read {peaks['lds_read_GBs']:.0f} GB/s, device copy {peaks['copy_GBs']:.0f} GB/s "
+        f"(LDS peak used {peak_lds:.0f} GB/s)")
+    kernels = {}
+    best = None
+    for sym, v in sorted(per_sym.items()):
+        sec = v["ms"] / 1e3
+        fr = {"hbm": v["hbm"] / sec / 1e9 / PEAK_HBM_GBS, "alu": v["alu"] / sec / 1e12 / PEAK_ALU_TOPS,
+              "lds": v["lds"] / sec / 1e9 / peak_lds}
+        kernels[sym] = {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"], "total_ms": v["ms"],
+                        "fracs": fr}
+        log(f"  {sym}: {v['launches']} launches, avg {v['ms'] / v['launches']:.3f} ms ({'; '.join(v['parts'])}), "
+            f"HBM {fr['hbm']:.2%}, ALU {fr['alu']:.2%}, LDS {fr['lds']:.2%}")
+        if best is None or v["ms"] > best[1]["ms"]:
+            best = (sym, v, fr)
+    out = None
+    if best:
+        sym, v, fr = best
+        bound = max(fr, key=fr.get)
+        per = {"hbm": v["hbm"], "alu": v["alu"], "lds": v["lds"]}[bound] / v["launches"]
+        sec = v["ms"] / 1e3 / v["launches"]
+        unit, scale, peak = {"hbm": ("GB/s", 1e9, PEAK_HBM_GBS), "alu": ("Tops/s", 1e12, PEAK_ALU_TOPS),
+                             "lds": ("GB/s", 1e9, peak_lds)}[bound]
+        out = {"bound": bound, "achieved": per / sec / scale, "peak": peak, "unit": unit, "frac": fr[bound],
+               "traffic": measured_traffic(sym, workload), "kernel": sym, "launches": v["launches"],
+               "launch_ms": v["ms"] / v["launches"], "algorithmic_per_launch": per, "fracs": fr,
+               "rule": "the counting kernel with the largest total time over the timed steps",
+               "peaks_measured": peaks, "kernels": kernels}
+    return out, phase
+
+
+# ---------------------------------------------------------------------- workloads
+
+class Workload:
+    """A resident graph, its orientation, workspaces and per-schedule options for ks."""
+
+    def __init__(self, arb, torch, name, n, off, idx, ks, eps, pv, a, log_prefix):
+        from paper_2002_10047_amd import learn, tuning
+        self.arb, self.torch, self.name, self.n, self.off, self.idx, self.ks, self.eps, self.pv = \
+            arb, torch, name, n, off, idx, ks, eps, pv
+        self.o = arb.arb_orient(off, idx, eps=eps)
+        self.m = idx.numel() // 2
+        self.wss = {k: arb.CountWorkspace(self.o["ooff"], self.o["oidx"], k) for k in ks}
+        self.totals = {k: torch.empty(1, dtype=torch.int64, device="cuda") for k in ks}
+        self.pvs = {k: torch.empty(n, dtype=torch.int64, device="cuda") for k in ks} if pv else {}
+        self.weights = {k: learn.load_weights(k) for k in ks}
+        missing = [k for k in ks if self.weights[k] is None]
+        if missing:
+            raise SystemExit(f"no trained cost model for k={missing}: run python -m paper_2002_10047_amd.train_cost")
+        self.feat = arb.arb_features(self.o["ooff"], self.o["oidx"], self.o["round"], self.o["rank"])
+        t_tune = time.time()
+        cache = a.tune_cache or tuning.CACHE
+        self.opts = {}
+        for sname in ("degree", "learned"):
+            per_k = {}
+            for k in ks:
+                w = self.weights[k] if sname == "learned" else None
+                f = self.feat if sname == "learned" else None
+                if a.no_tune:
+                    op = arb.count_opts(schedule=tuning.SCHEDULES[sname], mlp_weights=w, features=f)
+                else:
+                    op, _ = tuning.tuned_opts(self.o["ooff"], self.o["oidx"], k, sname, mlp_weights=w, features=f,
+                                              ws=self.wss[k], retune=a.retune, path=cache, log=log)
+                per_k[k] = op
+            self.opts[sname] = per_k
+        self.opts["plain"] = {k: arb.count_opts(schedule=arb.ARB_SCHED_PLAIN) for k in ks}
+        log(f"{log_prefix}: options ready in {time.time() - t_tune:.1f}s")
+
+    def step(self, sname, orient=True):
+        arb = self.arb
+        oo = arb.arb_orient(self.off, self.idx, eps=self.eps) if orient else self.o
+        if sname == "learned":
+            f = arb.arb_features(oo["ooff"], oo["oidx"], oo["round"], oo["rank"]) if orient else self.feat
+            for k in self.ks:
+                self.opts[sname][k].features = f.data_ptr()
+                self.opts[sname][k]._keep = (self.weights[k], f)
+        for k in self.ks:
+            arb.arb_count_async(oo["ooff"], oo["oidx"], k, total=self.totals[k], per_vertex=self.pvs.get(k),
+                                opts=self.opts[sname][k], ws=self.wss[k])
+        return oo
+
+    def read_totals(self):
+        import numpy as np
+        return {k: int(self.totals[k].cpu().numpy().view(np.uint64)[0]) for k in self.ks}
+
+    def timed(self, sname, steps, warmup, orient=True):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step(sname, orient)
+            torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            self.step(sname, orient)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        tot = self.read_totals()
+        log(f"{self.name} {sname}: {ms:.3f} ms/step over {steps} steps, totals {tot}")
+        return ms, tot
+
+    def phases(self, sname):
+        """orientation and per-k count times of one step (HIP events on the stream)."""
+        torch = self.torch
+        ks = self.ks
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2 + 2 * len(ks))]
+        torch.cuda.synchronize()
+        e[0].record()
+        o = self.arb.arb_orient(self.off, self.idx, eps=self.eps)
+        e[1].record()
+        for i, k in enumerate(ks):
+            e[2 + 2 * i].record()
+            self.arb.arb_count_async(o["ooff"], o["oidx"], k, total=self.totals[k], per_vertex=self.pvs.get(k),
+                                     opts=self.opts[sname][k], ws=self.wss[k])
+            e[3 + 2 * i].record()
+        torch.cuda.synchronize()
+        t_orient = e[0].elapsed_time(e[1]) / 1e3
+        return t_orient, {k: e[2 + 2 * i].elapsed_time(e[3 + 2 * i]) / 1e3 for i, k in enumerate(ks)}
+
+    def compare_schedules(self, main, ms_main, tot, steps, warmup):
+        cmp = {main: ms_main}
+        for sname in ("learned", "degree", "plain"):
+            if sname not in cmp:
+                ms_o, tot_o = self.timed(sname, steps, warmup)
+                if tot_o != tot:
+                    raise SystemExit(f"{self.name}: schedule {sname} changed the totals: {tot_o} vs {tot}")
+                cmp[sname] = ms_o
+        return {"ms_per_step": cmp, "learned_gain_vs_degree": cmp["degree"] / cmp["learned"],
+                "learned_gain_vs_plain": cmp["plain"] / cmp["learned"]}
 
 
 def main():
@@ -225,213 +461,105 @@ def main():
     from paper_2002_10047_amd import arb
     from paper_2002_10047_amd import graphgen as gg
 
-    ks = [int(x) for x in a.ks.split(",")]
-    arb.arb_profile_enable(True)
+    # ---------------------------------------------------------------- headline: 3-D RGG
+    ks = [5, 6, 7]
     t0 = time.time()
-    g = gg.config_graph("c2")
-    log(f"graph: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
-    off, idx = arb.to_device_csr(g)
-    o = arb.arb_orient(off, idx, eps=a.eps)
-    wss = {k: arb.CountWorkspace(o["ooff"], o["oidx"], k) for k in ks}
-    totals = {k: torch.empty(1, dtype=torch.int64, device="cuda") for k in ks}
-    from paper_2002_10047_amd import learn
-    weights = {k: learn.load_weights(k) for k in ks}
-    missing = [k for k in ks if weights[k] is None]
-    if missing:
-        raise SystemExit(f"no trained cost model for k={missing}: run python -m paper_2002_10047_amd.train_cost")
-    feat = arb.arb_features(o["ooff"], o["oidx"], o["round"], o["rank"])
-
-    # ---------------------------------------------------------------- tuning (untimed)
-    schedules = {}
-    t_tune = time.time()
-    from paper_2002_10047_amd import tuning
-    cache = a.tune_cache or tuning.CACHE
-    for name in ("degree", "learned"):
-        per_k = {}
-        for k in ks:
-            if a.no_tune:
-                op = arb.count_opts(schedule=tuning.SCHEDULES[name], mlp_weights=weights[k] if name == "learned" else None,
-                                    features=feat if name == "learned" else None)
-            else:
-                op, _ = tuning.tuned_opts(o["ooff"], o["oidx"], k, name, mlp_weights=weights[k] if name == "learned" else None,
-                                          features=feat if name == "learned" else None, ws=wss[k], retune=a.retune,
-                                          path=cache, log=log)
-            per_k[k] = op
-        schedules[name] = per_k
-    schedules["plain"] = {k: arb.count_opts(schedule=arb.ARB_SCHED_PLAIN) for k in ks}
-    log(f"tuning took {time.time() - t_tune:.1f}s")
-    arb.arb_profile_enable(True)      # the kernel timings cover the timed steps only, not tuning
-
-    def step(name):
-        oo = arb.arb_orient(off, idx, eps=a.eps)
-        if name == "learned":
-            f = arb.arb_features(oo["ooff"], oo["oidx"], oo["round"], oo["rank"])
-            for k in ks:
-                schedules[name][k].features = f.data_ptr()
-                schedules[name][k]._keep = (weights[k], f)
-        for k in ks:
-            arb.arb_count_async(oo["ooff"], oo["oidx"], k, total=totals[k], opts=schedules[name][k], ws=wss[k])
-        return oo
-
-    def timed(name):
-        for i in range(a.warmup):
-            step(name)
-            torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record()
-        for i in range(a.steps):
-            step(name)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / a.steps
-        tot = {k: int(totals[k].cpu().numpy().view(np.uint64)[0]) for k in ks}
-        log(f"{name}: {ms:.3f} ms/step over {a.steps} steps, totals {tot}")
-        return ms, tot
-
-    main_name = a.schedule if a.schedule != "persistent" else "degree"
-    ms_step, tot = timed(main_name)
+    n, off, idx = gg.rgg_cb_device(1 << 24, 40.0, seed=52)
+    torch.cuda.synchronize()
+    log(f"3-D RGG: n={n} m={idx.numel() // 2} generated on the GPU in {time.time() - t0:.1f}s")
+    hw = Workload(arb, torch, "rgg3d", n, off, idx, ks, a.eps, True, a, "rgg3d")
+    main_name = a.schedule
+    arb.arb_profile_enable(True)          # kernel timings cover the headline's timed steps only
+    ms_step, tot = hw.timed(main_name, a.steps, a.warmup)
+    prof = [e for e in arb.arb_profile_read() if not e["instrumented"]]
+    arb.arb_profile_enable(False)
     cliques = sum(tot.values())
-    value = cliques / (ms_step / 1e3)
+    exact = (golden("c5b") or {}).get("totals", {})
     out = {
         "metric": "k-cliques/s & oriented edges/s (exact), learned vs degree schedule, 1 GPU",
-        "value": value, "unit": "k-cliques/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "rmat20_k345", "graph": "R-MAT scale 20, 2^24 samples, a=.57 b=.19 c=.19 d=.05, "
-                   "seed 2, deduped", "n": g.n, "m": g.m, "k": ks, "eps": a.eps, "schedule": main_name,
-                   "opts": {str(k): arb.opts_dict(schedules[main_name][k]) for k in ks},
-                   "totals": {str(k): tot[k] for k in ks}},
+        "value": cliques / (ms_step / 1e3), "unit": "k-cliques/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "rgg3d_2^24_deg40_k567_per_vertex",
+                   "graph": "3-D random geometric graph on the unit torus, 2^24 vertices, mean degree 40, "
+                            "counter-based stream seed 52",
+                   "n": n, "m": hw.m, "k": ks, "per_vertex": True, "eps": a.eps, "schedule": main_name,
+                   "opts": {str(k): arb.opts_dict(hw.opts[main_name][k]) for k in ks},
+                   "totals": {str(k): tot[k] for k in ks},
+                   "totals_equal_oracle": ({str(k): tot[k] == exact[str(k)] for k in ks} if exact else None)},
     }
-    if not a.no_extras:
-        cmp = {main_name: ms_step}
-        for name in ("learned", "degree", "plain"):
-            if name not in cmp:
-                ms_o, tot_o = timed(name)
-                if tot_o != tot:
-                    raise SystemExit(f"schedule {name} changed the totals: {tot_o} vs {tot}")
-                cmp[name] = ms_o
-        out["schedules_ms_per_step"] = cmp
-        out["learned_gain_vs_degree"] = cmp["degree"] / cmp["learned"]
-        out["learned_gain_vs_plain"] = cmp["plain"] / cmp["learned"]
-        opts = schedules[main_name][ks[0]]
     if a.no_extras:
         copy_calibration(a, torch)
         print(json.dumps(out), flush=True)
         return
+    out["schedules"] = hw.compare_schedules(main_name, ms_step, tot, a.steps, a.warmup)
+    t_or, t_k = hw.phases(main_name)
+    out["orient_s"] = t_or
+    out["oriented_edges_per_s"] = hw.m / t_or
+    out["per_k"] = {str(k): {"count_s": t_k[k], "cliques": tot[k], "cliques_per_s": tot[k] / t_k[k]} for k in ks}
+    log(f"rgg3d orient {t_or * 1e3:.2f} ms ({hw.m / t_or:.3g} oriented edges/s); " +
+        ", ".join(f"k={k}: {t_k[k] * 1e3:.2f} ms" for k in ks))
+    rf, phase = roofline(arb, np, torch, hw.o, ks, True, hw.opts[main_name], prof, "rgg3d_k567_pv")
+    out["roofline"] = rf
+    for k, u in phase.items():
+        t = t_k[k]
+        out["per_k"][str(k)].update({"alu_Tops": u["alu"] / t / 1e12, "alu_frac": u["alu"] / t / 1e12 / PEAK_ALU_TOPS,
+                                     "lds_GBs": u["lds"] / t / 1e9, "hbm_GBs": u["hbm"] / t / 1e9})
+    off_h = idx_h = None
+    if not a.no_cpu_baseline:
+        off_h, idx_h = off.cpu().numpy(), idx.cpu().numpy()
+    del hw, off, idx
+    torch.cuda.empty_cache()
 
-    # ---------------------------------------------------------------- phase breakdown
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(2 + 2 * len(ks))]
-    torch.cuda.synchronize()
-    e[0].record()
-    o = arb.arb_orient(off, idx, eps=a.eps)
-    e[1].record()
-    for i, k in enumerate(ks):
-        e[2 + 2 * i].record()
-        arb.arb_count_async(o["ooff"], o["oidx"], k, total=totals[k], opts=schedules[main_name][k], ws=wss[k])
-        e[3 + 2 * i].record()
-    torch.cuda.synchronize()
-    t_orient = e[0].elapsed_time(e[1]) / 1e3
-    per_k = {}
-    for i, k in enumerate(ks):
-        tk = e[2 + 2 * i].elapsed_time(e[3 + 2 * i]) / 1e3
-        per_k[str(k)] = {"count_s": tk, "cliques": tot[k], "cliques_per_s": tot[k] / tk}
-    out["oriented_edges_per_s"] = g.m / t_orient
-    out["orient_s"] = t_orient
-    out["per_k"] = per_k
-    log(f"orient {t_orient * 1e3:.3f} ms; per k: " +
-        ", ".join(f"k={k}: {v['count_s'] * 1e3:.3f} ms" for k, v in per_k.items()))
+    # ---------------------------------------------------------------- R-MAT scale 26, k = 4
+    if not a.no_rmat26:
+        t0 = time.time()
+        n26, off26, idx26 = gg.rmat_cb_device(26, 1 << 30, seed=51)
+        torch.cuda.synchronize()
+        log(f"R-MAT 26: n={n26} m={idx26.numel() // 2} generated on the GPU in {time.time() - t0:.1f}s")
+        w26 = Workload(arb, torch, "rmat26", n26, off26, idx26, [4], a.eps, False, a, "rmat26")
+        ms26, tot26 = w26.timed(main_name, 2, 1)
+        sch = w26.compare_schedules(main_name, ms26, tot26, 2, 1)
+        t_or, t_k = w26.phases(main_name)
+        out["rmat26_k4"] = {"n": n26, "m": w26.m, "total": tot26[4], "orient_s": t_or,
+                            "oriented_edges_per_s": w26.m / t_or, "count_s": t_k[4],
+                            "cliques_per_s": tot26[4] / t_k[4], "step_ms": sch["ms_per_step"],
+                            "learned_gain_vs_degree": sch["learned_gain_vs_degree"],
+                            "learned_gain_vs_plain": sch["learned_gain_vs_plain"],
+                            "opts": arb.opts_dict(w26.opts[main_name][4])}
+        log(f"rmat26 k=4: {out['rmat26_k4']}")
+        del w26, off26, idx26
+        torch.cuda.empty_cache()
 
-    # ---------------------------------------------------------------- roofline
-    # every counting-kernel launch of this run was timed with HIP events on its own
-    # stream; a kernel symbol k_count<W, depth, 0, 0> serves tier W and depth max(1, k-3)
-    prof = [e for e in arb.arb_profile_read() if not e["per_vertex"] and not e["instrumented"]]
-    arb.arb_profile_enable(False)
-    d, W, gather, nodes = algorithmic_units(arb, o, ks, np)
-    tw = [2, 4, 8, 12, 16, 24]
-    per_sym = {}
-    phase_units = {}            # per k: algorithmic units of one count (all tiers)
-    peaks = measure_peaks(torch)
-    peak_lds = max(SPEC_LDS_GBS, peaks["lds_read_GBs"] or 0.0)
-    log(f"probes: LDS read {peaks['lds_read_GBs']:.0f} GB/s, device copy {peaks['copy_GBs']:.0f} GB/s "
-        f"(LDS peak used {peak_lds:.0f} GB/s)")
-    for e in prof:
-        k, ti = e["k"], e["tier"]
-        live = d >= k - 1
-        td = tier_of(d)
-        if k >= 5:
-            td = np.minimum(td, 5)       # above 768 out-neighbours: per-out-neighbour items in tier 5
-        sel = live & (td == ti)
-        hbm_bytes = float(4 * (d[sel] + 4 * d[sel] + gather[sel]).sum() + 16 * sel.sum())
-        alu_ops = lds_bytes = 0.0
-        if k >= 4:
-            ck2 = nodes[k][sel] - nodes[k - 1][sel]          # c_{k-2}(v)
-            deep = nodes[k][sel] - d[sel]                    # sum_{j=2}^{k-2} c_j(v)
-            # every node of depth >= 2 ANDs W words; nodes of depth k-2 also popcount them
-            alu_ops = float((W[sel] * (deep + ck2)).sum())
-            # bit rows built (d), a row read and I' written per internal node (depth
-            # 1..k-3), a row read per node of depth k-2: 4 W (d + 2 sum_{j<=k-3} c_j + c_{k-2})
-            lds_bytes = float((4 * W[sel] * (d[sel] + nodes[k - 1][sel] + nodes[k][sel])).sum())
-        sym = f"k_count<{tw[ti]},{max(1, k - 3)},0,0>" if ti < len(tw) else "k_count_big<0,0>"
-        s_ = per_sym.setdefault(sym, dict(launches=0, ms=0.0, hbm=0.0, alu=0.0, lds=0.0, parts=[]))
-        s_["launches"] += e["launches"]
-        s_["ms"] += e["total_ms"]
-        s_["hbm"] += e["launches"] * hbm_bytes
-        s_["alu"] += e["launches"] * alu_ops
-        s_["lds"] += e["launches"] * lds_bytes
-        pk = phase_units.setdefault(k, dict(alu=0.0, lds=0.0, hbm=0.0))
-        pk["alu"] += alu_ops
-        pk["lds"] += lds_bytes
-        pk["hbm"] += hbm_bytes
-        s_["parts"].append(f"k={k}: {e['launches']} launches, {e['total_ms'] / e['launches']:.3f} ms avg")
-    best = None
-    for sym, v in sorted(per_sym.items()):
-        sec = v["ms"] / 1e3
-        hbm = v["hbm"] / sec / 1e9
-        alu = v["alu"] / sec / 1e12
-        lds = v["lds"] / sec / 1e9
-        log(f"  {sym}: {v['launches']} launches, avg {v['ms'] / v['launches']:.3f} ms ({'; '.join(v['parts'])}), "
-            f"algorithmic {hbm:.0f} GB/s ({hbm / PEAK_HBM_GBS:.2%} of HBM), {alu:.2f} Tops ({alu / PEAK_ALU_TOPS:.2%} "
-            f"of ALU), LDS {lds:.0f} GB/s ({lds / peak_lds:.2%})")
-        if best is None or v["ms"] > best[1]["ms"]:
-            best = (sym, v, hbm, alu, lds)
-    if best:
-        sym, v, hbm, alu, lds = best
-        fr = {"hbm": hbm / PEAK_HBM_GBS, "alu": alu / PEAK_ALU_TOPS, "lds": lds / peak_lds}
-        bound = max(fr, key=fr.get)
-        unit = {"hbm": ("GB/s", hbm, PEAK_HBM_GBS), "alu": ("Tops/s", alu, PEAK_ALU_TOPS),
-                "lds": ("GB/s", lds, peak_lds)}[bound]
-        out["roofline"] = {"bound": bound, "achieved": unit[1], "peak": unit[2], "unit": unit[0], "frac": fr[bound]}
-        out["roofline"]["traffic"] = measured_traffic(sym)
-        out["roofline"]["kernel"] = sym
-        out["roofline"]["launches"] = v["launches"]
-        out["roofline"]["launch_ms"] = v["ms"] / v["launches"]
-        out["roofline"]["algorithmic_per_launch"] = {"hbm": v["hbm"], "alu": v["alu"], "lds": v["lds"]}[bound] / \
-            v["launches"]
-        out["roofline"]["fracs"] = fr
-        out["roofline"]["lds_words_per_s"] = lds * 1e9 / 4
-        out["roofline"]["peaks_measured"] = peaks
-    # whole count of each k (all tier kernels, concurrent): algorithmic rates over its time
-    for k, u in phase_units.items():
-        if str(k) in per_k:
-            t = per_k[str(k)]["count_s"]
-            per_k[str(k)]["alu_Tops"] = u["alu"] / t / 1e12
-            per_k[str(k)]["alu_frac"] = u["alu"] / t / 1e12 / PEAK_ALU_TOPS
-            per_k[str(k)]["lds_GBs"] = u["lds"] / t / 1e9
-            per_k[str(k)]["hbm_GBs"] = u["hbm"] / t / 1e9
+    # ---------------------------------------------------------------- R-MAT scale 20, k = 3, 4, 5
+    g = gg.config_graph("c2")
+    off20, idx20 = arb.to_device_csr(g)
+    w20 = Workload(arb, torch, "rmat20", g.n, off20, idx20, [3, 4, 5], a.eps, False, a, "rmat20")
+    ms20, tot20 = w20.timed(main_name, a.steps, a.warmup)
+    sch = w20.compare_schedules(main_name, ms20, tot20, a.steps, a.warmup)
+    t_or, t_k = w20.phases(main_name)
+    out["rmat20_k345"] = {"n": g.n, "m": g.m, "totals": {str(k): v for k, v in tot20.items()}, "orient_s": t_or,
+                          "oriented_edges_per_s": g.m / t_or, "count_s": {str(k): t for k, t in t_k.items()},
+                          "step_ms": sch["ms_per_step"], "value": sum(tot20.values()) / (ms20 / 1e3),
+                          "learned_gain_vs_degree": sch["learned_gain_vs_degree"],
+                          "learned_gain_vs_plain": sch["learned_gain_vs_plain"]}
 
-    if a.no_studies:
-        if not a.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline(g, ks, a.cpu_seconds)
-        copy_calibration(a, torch)
-        print(json.dumps(out), flush=True)
-        return
+    if not a.no_studies:
+        studies(arb, gg, torch, g, off20, idx20, w20, tot20, a, out)
+    del w20
 
-    # ---------------------------------------------------------------- colorful sparsification
-    # approximate counts (Sec. 3.3): sparsify with c colours, orient and count the sparsified
-    # graph; time of the three (wall clock, synchronised) and the estimate's relative error
+    # ---------------------------------------------------------------- CPU oracle baseline
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, off_h, idx_h, ks, a.cpu_seconds, exact)
+    copy_calibration(a, torch)
+    print(json.dumps(out), flush=True)
+
+
+def studies(arb, gg, torch, g, off, idx, w20, tot, a, out):
+    """The paper's other rows on R-MAT 20: colorful sparsification (Sec. 3.3), the
+    orderings of Sec. 5 and arb-approx-peel (Sec. 4.2)."""
+    kx = max(w20.ks)
     approx = {}
-    kx = max(ks)
     for c in (2, 4, 8):
         col = torch.from_numpy(gg.colors(g.n, c, 7)).cuda()
         torch.cuda.synchronize()
@@ -444,10 +572,6 @@ def main():
         approx[str(c)] = {"k": kx, "seconds": dt, "kept_edges": int(sidx.numel() // 2), "count": cnt,
                           "estimate": est, "rel_error": (est - tot[kx]) / tot[kx] if tot[kx] else None}
     out["colorful_sparsification"] = approx
-
-    # ---------------------------------------------------------------- orientation study
-    # the orderings the paper compares (Sec. 5): orientation time, largest out-degree and
-    # the count of the largest k on each (degree schedule, library defaults)
     study = {}
     for name, meth in (("peel", arb.ARB_ORIENT_PEEL), ("degree", arb.ARB_ORIENT_DEGREE),
                        ("goodrich_pszona", arb.ARB_ORIENT_GOODRICH_PSZONA), ("kcore", arb.ARB_ORIENT_KCORE)):
@@ -469,19 +593,10 @@ def main():
                        f"count_k{kx}_ms": t_ct * 1e3}
         del wsx
     out["orientation_study"] = study
-
-    # ---------------------------------------------------------------- approximate peeling
-    # arb-approx-peel (Sec. 4.2) for k = 3 on the same graph
     torch.cuda.synchronize()
     t1 = time.time()
-    dens, rounds, _ = arb.arb_approx_peel(o["ooff"], o["oidx"], 3, 1.0)
+    dens, rounds, _ = arb.arb_approx_peel(w20.o["ooff"], w20.o["oidx"], 3, 1.0)
     out["approx_peel"] = {"k": 3, "eps": 1.0, "seconds": time.time() - t1, "rounds": rounds, "density": dens}
-
-    # ---------------------------------------------------------------- CPU oracle baseline
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, ks, a.cpu_seconds)
-    copy_calibration(a, torch)
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

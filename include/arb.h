@@ -50,7 +50,7 @@ enum {
     ARB_EMISMATCH = 6    /* two schedules gave different totals (a library defect) */
 };
 
-#define ARB_MAX_K 10            /* largest clique size the counting kernels take */
+#define ARB_MAX_K 32            /* largest clique size the counting kernels take */
 #define ARB_MAX_LOCAL 768       /* largest candidate set held in LDS per work item */
 #define ARB_MAX_ROUNDS 64       /* peel rounds recorded in the round statistics */
 #define ARB_MAX_ROW_SORT 16384  /* longest directed row the orientation can sort */
@@ -183,6 +183,15 @@ typedef struct {
     int concurrent_tiers;  /* nonzero: the tier kernels of a call run side by side on
                               library streams forked from and joined back into `stream`
                               by events (persistent schedules, profiling off) */
+    int tier_fill;         /* LDS tile per item, 10..100 (%): an item goes to the first tier
+                              (64, 128, 256, 384, 512, 768 local vertices) whose capacity
+                              times tier_fill / 100 holds its set, so lower values give
+                              items larger tiles and teams of more waves; 100 = the
+                              smallest tier that fits */
+    int big_max_degree;    /* roots with ARB_MAX_LOCAL < d+ <= big_max_degree are counted
+                              whole by the global-scratch kernel (bit rows in the
+                              workspace), larger ones as one (root, child) item per
+                              out-neighbour; -1 = as large as the workspace allows */
     const uint16_t *mlp_weights; /* device bf16 weights for ARB_SCHED_LEARNED (8641) */
     const float *features;       /* device float[n][3] from arb_features, ARB_SCHED_LEARNED */
 } arb_count_opts;
@@ -220,6 +229,15 @@ size_t arb_count_workspace(int64_t n, int64_t m, int k);
 int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,
                     uint64_t *per_root, uint64_t *work_out, const arb_count_opts *opts,
                     void *ws, size_t ws_bytes, void *stream);
+
+/* The per-root work measure of the learned schedule (its training label): work_out[v]
+ * (device uint64[n], overwritten) = w(v) as for arb_count_async's work_out; cycles_out
+ * (device uint64[n], nullable, overwritten) = shader clock cycles (s_memtime) the team
+ * spent on root v's items, a timing and not reproducible.  Runs the unsplit schedule
+ * given by opts (nullable: defaults).  Workspace: arb_count_workspace(n, m, k).
+ * Asynchronous; errors as arb_count_async. */
+int arb_count_instrumented(const arb_ocsr *dg, int k, uint64_t *work_out, uint64_t *cycles_out,
+                           const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /* out[g] = sum of in[offsets[g] .. offsets[g+1]) for g < G (device arrays; offsets has
  * G+1 entries).  With per_root counts mapped to original ids (arb_permute_u64) and a
@@ -260,7 +278,9 @@ int arb_profile_read(int max_entries, int32_t *tier, int32_t *k, int32_t *per_ve
 /*
  * Autotuner: coordinate descent (two passes) over the split threshold
  * (split_min_degree, or split_min_cost for ARB_SCHED_LEARNED), persist_blocks_per_cu,
- * chunk_small, bitmap_max_span and concurrent_tiers for this graph and k.  Each candidate runs once to
+ * chunk_small, bitmap_max_span (id-range bitmap vs hash membership), concurrent_tiers,
+ * tier_fill (LDS tile and waves per item) and big_max_degree (whole big roots in global
+ * scratch vs per-out-neighbour items) for this graph and k.  Each candidate runs once to
  * warm up and then `trials` times; its time is the fastest run (HIP events on the
  * stream).  Every candidate's total must equal the first one's, else ARB_EMISMATCH.
  * opts: in, the schedule (and weights/features when learned) and starting values;
@@ -269,6 +289,14 @@ int arb_profile_read(int max_entries, int32_t *tier, int32_t *k, int32_t *per_ve
  */
 int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int trials, float *best_ms,
                  void *ws, size_t ws_bytes, void *stream);
+
+/* The autotuner's search space: the candidate values of dimension `dim` (ARB_TUNE_*)
+ * are written to values (host, up to max_values entries, as doubles); returns how many
+ * candidates the dimension has, or -1 for an unknown dim. */
+enum { ARB_TUNE_SPLIT_MIN_DEGREE = 0, ARB_TUNE_SPLIT_MIN_COST = 1, ARB_TUNE_BLOCKS_PER_CU = 2,
+       ARB_TUNE_CHUNK_SMALL = 3, ARB_TUNE_BITMAP_MAX_SPAN = 4, ARB_TUNE_CONCURRENT_TIERS = 5,
+       ARB_TUNE_TIER_FILL = 6, ARB_TUNE_BIG_MAX_DEGREE = 7 };
+int arb_autotune_space(int dim, int max_values, double *values);
 
 /* ---------------------------------------------------------------- learned schedule */
 

@@ -17,7 +17,7 @@
  *                           count is the plain definition: every k-vertex subset whose
  *                           pairs are all adjacent, counted once from its first vertex)
  *   orc_brute               brute force over all k-subsets, n <= 64
- *   orc_degeneracy          exact degeneracy (k-core / Matula-Beck order)
+ *   orc_degeneracy          exact degeneracy (k-core decomposition by bin sort, Batagelj-Zaversnik 2003)
  *   orc_local_cliques       c_j(v) = number of j-cliques inside G[N+(v)] of a directed
  *                           graph (the per-root subproblem of Alg. 1)
  *   orc_local_cliques_roots the same for a list of roots (sampled checks of large graphs)
@@ -407,7 +407,8 @@ uint64_t orc_brute(int64_t n, const int64_t *off, const int32_t *idx, int k, uin
 /* ------------------------------------------------------------------ degeneracy */
 
 /* Exact degeneracy: the largest minimum degree seen while repeatedly deleting a
- * vertex of minimum current degree (Matula-Beck bucket order). */
+ * vertex of minimum current degree, kept in degree bins (the bin-sort core decomposition
+ * of Batagelj and Zaversnik, 2003). */
 int64_t orc_degeneracy(int64_t n, const int64_t *off, const int32_t *idx)
 {
     if (n == 0) return 0;

@@ -32,7 +32,7 @@ def _define(name):
     return int(m.group(1)) if m else None
 
 
-ARB_MAX_K = _define("ARB_MAX_K") or 12
+ARB_MAX_K = _define("ARB_MAX_K") or 10
 ARB_MAX_LOCAL = _define("ARB_MAX_LOCAL") or 768
 ARB_MAX_ROUNDS = _define("ARB_MAX_ROUNDS") or 64
 ARB_MLP_PARAMS = _define("ARB_MLP_PARAMS") or 8641
@@ -58,6 +58,7 @@ class ArbCountOpts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("split_min_degree", ctypes.c_int),
                 ("split_min_cost", ctypes.c_float), ("persist_blocks_per_cu", ctypes.c_int),
                 ("chunk_small", ctypes.c_int), ("bitmap_max_span", ctypes.c_int), ("concurrent_tiers", ctypes.c_int),
+                ("tier_fill", ctypes.c_int), ("big_max_degree", ctypes.c_int),
                 ("mlp_weights", ctypes.c_void_p),
                 ("features", ctypes.c_void_p)]
 
@@ -87,6 +88,7 @@ _sigs = {
     "arb_count_async": ([P, I32, P, P, P, P, P, P, SZ, P], I32),
     "arb_segment_sum_u64": ([P, P, I64, P, P], I32),
     "arb_count": ([P, I32, P, P, P, SZ, P], ctypes.c_uint64),
+    "arb_count_instrumented": ([P, I32, P, P, P, P, SZ, P], I32),
     "arb_features": ([P, P, P, P, P], I32),
     "arb_mlp_forward": ([P, P, I64, P, P, P], I32),
     "arb_mlp_workspace": ([I64], SZ),
@@ -95,6 +97,7 @@ _sigs = {
     "arb_adam_step": ([P, P, P, P, P, FLT, I32, P], I32),
     "arb_to_bf16": ([P, P, I64, P], I32),
     "arb_autotune": ([P, I32, P, I32, P, P, SZ, P], I32),
+    "arb_autotune_space": ([I32, I32, P], I32),
     "arb_profile_enable": ([I32], I32),
     "arb_profile_read": ([I32, P, P, P, P, P, P], I32),
     "arb_last_error": ([], I32),
@@ -342,7 +345,7 @@ def arb_permute_u64(rank, values, stream=None):
 
 def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost=0.0,
                persist_blocks_per_cu=8, chunk_small=16, mlp_weights=None, features=None, bitmap_max_span=1 << 30,
-               concurrent_tiers=1):
+               concurrent_tiers=1, tier_fill=100, big_max_degree=-1):
     o = ArbCountOpts()
     _lib.arb_count_default_opts(ctypes.byref(o))
     o.schedule = int(schedule)
@@ -352,6 +355,8 @@ def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost
     o.chunk_small = int(chunk_small)
     o.bitmap_max_span = int(bitmap_max_span)
     o.concurrent_tiers = int(concurrent_tiers)
+    o.tier_fill = int(tier_fill)
+    o.big_max_degree = int(big_max_degree)
     o.mlp_weights = mlp_weights.data_ptr() if mlp_weights is not None else None
     o.features = features.data_ptr() if features is not None else None
     o._keep = (mlp_weights, features)
@@ -361,7 +366,8 @@ def count_opts(schedule=ARB_SCHED_PERSISTENT, split_min_degree=0, split_min_cost
 def opts_dict(o):
     return {"schedule": o.schedule, "split_min_degree": o.split_min_degree, "split_min_cost": o.split_min_cost,
             "persist_blocks_per_cu": o.persist_blocks_per_cu, "chunk_small": o.chunk_small,
-            "bitmap_max_span": o.bitmap_max_span, "concurrent_tiers": o.concurrent_tiers}
+            "bitmap_max_span": o.bitmap_max_span, "concurrent_tiers": o.concurrent_tiers, "tier_fill": o.tier_fill,
+            "big_max_degree": o.big_max_degree}
 
 
 def arb_autotune(ooff, oidx, k, opts, trials=3, ws=None, stream=None):
@@ -373,6 +379,23 @@ def arb_autotune(ooff, oidx, k, opts, trials=3, ws=None, stream=None):
     _check(_lib.arb_autotune(ctypes.byref(dg), int(k), ctypes.byref(opts), int(trials), ctypes.byref(ms), _ptr(ws.buf),
                              ws.buf.numel(), _stream(stream)), "arb_autotune")
     return float(ms.value)
+
+
+TUNE_DIMS = {"split_min_degree": 0, "split_min_cost": 1, "persist_blocks_per_cu": 2, "chunk_small": 3,
+             "bitmap_max_span": 4, "concurrent_tiers": 5, "tier_fill": 6, "big_max_degree": 7}
+
+
+def arb_autotune_space():
+    """{option name: candidate values} of arb_autotune's search."""
+    out = {}
+    for name, dim in TUNE_DIMS.items():
+        cnt = _lib.arb_autotune_space(dim, 0, None)
+        if cnt < 0:
+            raise ArbError(arb_last_error(), "arb_autotune_space")
+        buf = (ctypes.c_double * max(cnt, 1))()
+        _lib.arb_autotune_space(dim, cnt, buf)
+        out[name] = [float(x) if name == "split_min_cost" else int(x) for x in buf[:cnt]]
+    return out
 
 
 class CountWorkspace:
@@ -397,6 +420,21 @@ def arb_count_async(ooff, oidx, k, total=None, per_vertex=None, work=None, opts=
                               _stream(stream))
     _check(rc, "arb_count_async")
     return total
+
+
+def arb_count_instrumented(ooff, oidx, k, cycles=False, opts=None, ws=None, stream=None):
+    """(work, cycles or None): per-root work measure and, if asked, clock cycles per root
+    (device int64 tensors holding uint64)."""
+    dg = _ocsr(ooff, oidx)
+    n = ooff.numel() - 1
+    if ws is None:
+        ws = CountWorkspace(ooff, oidx, k)
+    work = torch.empty(max(n, 1), dtype=torch.int64, device=ooff.device)
+    cyc = torch.empty(max(n, 1), dtype=torch.int64, device=ooff.device) if cycles else None
+    _check(_lib.arb_count_instrumented(ctypes.byref(dg), int(k), _ptr(work), _ptr(cyc),
+                                       ctypes.byref(opts) if opts is not None else None, _ptr(ws.buf), ws.buf.numel(),
+                                       _stream(stream)), "arb_count_instrumented")
+    return work[:n], (cyc[:n] if cyc is not None else None)
 
 
 def arb_count_batch_workspace(n: int, m: int, k: int, G: int) -> int:

@@ -14,7 +14,7 @@ PROBE_SOURCES = ["peaks.hip"]
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["prims.hip", "orient.hip", "count.hip", "count_big.hip", "mlp.hip", "abi.hip", "sparsify.hip",
            "approx_peel.hip", "peel.hip"] + \
-    [f"count_d{i}.hip" for i in range(1, 8)]
+    [f"count_d{i}.hip" for i in range(1, 9)]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -71,9 +71,10 @@ __global__ void k_finish(const int32_t *err, unsigned long long *total) {
 
 constexpr int kCostBits = 13;                 // schedule key: tier (3 bits) above the cost
 constexpr uint32_t kCostMax = (1u << kCostBits) - 1;
-constexpr int kBigTier = kNumTiers;        // roots above the LDS tiers (k = 3, 4)
+constexpr int kBigTier = kNumTiers;        // roots above the LDS tiers, d+ <= dbig
 constexpr int kDeadTier = 7;
 constexpr int kMaxParts = 64;
+constexpr int64_t kOvfCap = 1 << 20;          // overflowed pair items the big kernel can take
 
 // Parts of a root: degree schedule P = ceil(d / split_deg); learned schedule
 // P = ceil(2^(y - split_cost)) with y the predicted log2(1 + work); at most 64 and at
@@ -91,8 +92,19 @@ __device__ __forceinline__ int root_parts(int64_t d, int split_deg, const float 
     return (int)(P < 1 ? 1 : P);
 }
 
+// Tier of an item with a set of d vertices: the first tier whose capacity times fill / 100
+// holds d (larger tiles and teams for lower fill), -1 above the largest tier.
+__device__ __forceinline__ int tier_of_fill(int64_t d, int fill) {
+    constexpr int cap[kNumTiers] = {64, 128, 256, 384, 512, 768};
+    const int t0 = tier_of(d);
+    if (t0 < 0) return -1;
+    for (int t = t0; t < kNumTiers; ++t)
+        if (d * 100 <= (int64_t)cap[t] * fill) return t;
+    return kNumTiers - 1;
+}
+
 __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *lcost, int split_deg, float split_cost,
-                            int dbig, uint32_t *key, int32_t *val, int32_t *parts) {
+                            int dbig, int fill, uint32_t *key, int32_t *val, int32_t *parts) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = off[v + 1] - off[v];
         uint32_t kk;
@@ -100,11 +112,11 @@ __global__ void k_root_keys(int64_t n, const int64_t *off, int k, const float *l
         if (d < k - 1) {
             kk = ((uint32_t)kDeadTier << kCostBits) | kCostMax;
         } else {
-            int t = tier_of(d);
+            int t = tier_of_fill(d, fill);
             // the learned cost is evaluated for roots above the 64-tier only (its light
             // roots balance under any order); the 64-tier keeps the degree cost
             const float *lc = t == 0 ? nullptr : lcost;
-            if (t < 0 && (k == 3 || k == 4) && d <= dbig) {
+            if (t < 0 && d <= dbig) {
                 t = kBigTier;                  // whole root, bit rows in global scratch
                 P = 1;
             } else if (t < 0) {                // per-out-neighbour items in the largest tier
@@ -205,8 +217,11 @@ struct CountWs {
     int32_t *parts;       // n
     float *lcost;         // n
     unsigned long long *tot;  // total of the synchronous arb_count
-    uint32_t *big_rows;       // big-root bit rows: big_teams slices of big_words words
+    uint32_t *big_rows;       // big-item bit rows: big_teams slices of big_words words
     int64_t big_teams, big_words;
+    int64_t *ovf_items;       // pair items overflowing the LDS tiers (ovf_cap entries)
+    unsigned long long *ovf_count;
+    int64_t ovf_cap;
     int dbig;
     void *scan_ws, *radix_ws;
 };
@@ -229,10 +244,13 @@ static size_t carve_count(Carver &c, int64_t n, int64_t m, int k, CountWs *w) {
     w->tot = c.take<unsigned long long>(4);
     w->scan_ws = c.take<char>(scan_workspace(nn + 1));
     w->radix_ws = c.take<char>(radix_workspace(nn));
-    w->dbig = (k == 3 || k == 4) ? big_dmax(m) : 0;
+    w->dbig = k >= 3 ? big_dmax(m) : 0;
     w->big_teams = w->dbig ? big_teams(m) : 0;
     w->big_words = w->dbig ? big_team_words(w->dbig) : 0;
     w->big_rows = c.take<uint32_t>(w->big_teams * w->big_words > 0 ? w->big_teams * w->big_words : 1);
+    w->ovf_cap = w->dbig ? (m < kOvfCap ? (m > 0 ? m : 1) : kOvfCap) : 0;
+    w->ovf_items = c.take<int64_t>(w->ovf_cap > 0 ? w->ovf_cap : 1);
+    w->ovf_count = c.take<unsigned long long>(1);
     return c.used;
 }
 
@@ -262,6 +280,8 @@ struct Profile {
     std::vector<ProfTotal> totals;
 };
 static Profile g_prof;
+// set while launch-timing events must not be created
+static thread_local bool g_no_events = false;
 
 static int prof_event(hipEvent_t *e) {
     if (!g_prof.pool.empty()) {
@@ -318,8 +338,8 @@ static int launch_count(int depth, int tier, bool pv, bool instr, const CountArg
         case 5: return launch_count_depth5(tier, pv, instr, a, grid, s);
         case 6: return launch_count_depth6(tier, pv, instr, a, grid, s);
         case 7: return launch_count_depth7(tier, pv, instr, a, grid, s);
+        default: return launch_count_depth8(tier, pv, instr, a, grid, s);     // any deeper walk
     }
-    return ARB_EINVAL;
 }
 
 static int device_cus() {
@@ -346,6 +366,8 @@ extern "C" void arb_count_default_opts(arb_count_opts *o) {
     o->chunk_small = 16;
     o->bitmap_max_span = 1 << 30;
     o->concurrent_tiers = 1;
+    o->tier_fill = 100;
+    o->big_max_degree = -1;
     o->mlp_weights = nullptr;
     o->features = nullptr;
 }
@@ -386,12 +408,17 @@ extern "C" int arb_check_oriented(const arb_ocsr *dg, void *ws, size_t ws_bytes,
 // roff/ridx (nullable): the candidate set of each root in place of N+(v) -- any sorted
 // set of vertices whose every (k-1)-clique, with the root, is a k-clique to count
 // (arb-peel's updates); the workspace must then be sized for max(m, rnnz) arcs.
+// root_ids (nullable, device): the roots are the nroots vertices listed there, root i with
+// candidate set ridx[roff[i] .. roff[i + 1]) (roff then has nroots + 1 entries); only they
+// are scheduled.  pv_zeroed: per_vertex already holds zeros (it is added to, not cleared).
 int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *per_root_out,
                      uint64_t *work_out, const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s,
-                     const int64_t *roff, const int32_t *ridx, int64_t rnnz) {
+                     const int64_t *roff, const int32_t *ridx, int64_t rnnz, uint64_t *cycles_out,
+                     const int32_t *root_ids, int64_t nroots, bool pv_zeroed) {
     if (!ocsr_ok(dg) || !total_dev || !ws) return ARB_EINVAL;
     if (k < 1 || k > ARB_MAX_K) return ARB_EINVAL;
     if (roff && (!ridx || k < 3)) return ARB_EINVAL;
+    if (root_ids && (!roff || nroots < 0 || nroots > dg->n || work_out || cycles_out)) return ARB_EINVAL;
     const int64_t mw = roff && rnnz > dg->m ? rnnz : dg->m;     // arcs the item arrays must hold
     if (!roff) {
         roff = dg->offsets;
@@ -401,21 +428,24 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
     arb_count_default_opts(&opts);
     if (opts_in) opts = *opts_in;
     if (opts.schedule < 0 || opts.schedule > 2) return ARB_EINVAL;
-    if (opts.schedule == ARB_SCHED_LEARNED && (!opts.mlp_weights || !opts.features)) return ARB_EINVAL;
+    if (opts.schedule == ARB_SCHED_LEARNED && (!opts.mlp_weights || !opts.features || root_ids)) return ARB_EINVAL;
     if (opts.persist_blocks_per_cu < 1 || opts.persist_blocks_per_cu > 8) return ARB_EINVAL;
     if (opts.chunk_small < 1 || opts.chunk_small > 256) return ARB_EINVAL;
     if (opts.bitmap_max_span < 0) return ARB_EINVAL;
     if (opts.split_min_degree < 0 || !(opts.split_min_cost >= 0.f)) return ARB_EINVAL;
+    if (opts.tier_fill < 10 || opts.tier_fill > 100 || opts.big_max_degree < -1) return ARB_EINVAL;
     const int64_t n = dg->n, m = dg->m;
     if (ws_bytes < arb_count_workspace(n, mw, k)) return ARB_EWORKSPACE;
     unsigned long long *total = reinterpret_cast<unsigned long long *>(total_dev);
     unsigned long long *pv = reinterpret_cast<unsigned long long *>(per_vertex);
     unsigned long long *work = reinterpret_cast<unsigned long long *>(work_out);
+    unsigned long long *cycles = work ? reinterpret_cast<unsigned long long *>(cycles_out) : nullptr;
     unsigned long long *per_root = reinterpret_cast<unsigned long long *>(per_root_out);
     int rc;
     const unsigned gb = grid_for(n, 256, 4096);
-    if (pv) { k_u64_fill<<<gb, 256, 0, s>>>(pv, 0ull, n); ARB_CHECK_LAUNCH(); }
+    if (pv && !pv_zeroed) { k_u64_fill<<<gb, 256, 0, s>>>(pv, 0ull, n); ARB_CHECK_LAUNCH(); }
     if (work) { k_u64_fill<<<gb, 256, 0, s>>>(work, 0ull, n); ARB_CHECK_LAUNCH(); }
+    if (cycles) { k_u64_fill<<<gb, 256, 0, s>>>(cycles, 0ull, n); ARB_CHECK_LAUNCH(); }
     if (per_root) { k_u64_fill<<<gb, 256, 0, s>>>(per_root, 0ull, n); ARB_CHECK_LAUNCH(); }
     if (per_root && k <= 2) {
         if (k == 1) k_u64_fill<<<gb, 256, 0, s>>>(per_root, 1ull, n);
@@ -426,7 +456,10 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
     if (k == 2) { k_count_k2<<<gb, 256, 0, s>>>(n, dg->offsets, dg->indices, total, pv); ARB_CHECK_LAUNCH(); return ARB_OK; }
     k_u64_fill<<<1, 64, 0, s>>>(total, 0ull, 1);
     ARB_CHECK_LAUNCH();
-    if (n == 0) return ARB_OK;
+    // roots scheduled: every vertex, or the listed ones
+    const int64_t ns = root_ids ? nroots : n;
+    const unsigned gs = grid_for(ns, 256, 4096);
+    if (ns == 0) return ARB_OK;
 
     Carver cv(ws);
     CountWs w;
@@ -434,6 +467,8 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
     if ((rc = fill_i32(w.err, 0, 4, s))) return rc;
     if ((rc = fill_i32(w.heads, 0, 16, s))) return rc;
     if ((rc = fill_i64(w.seg, 0, 16, s))) return rc;
+    k_u64_fill<<<1, 64, 0, s>>>(w.ovf_count, 0ull, 1);
+    ARB_CHECK_LAUNCH();
 
     const bool learned = opts.schedule == ARB_SCHED_LEARNED && !work;
     const float *lcost = nullptr;
@@ -443,16 +478,17 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
     }
     const int split_deg = work ? 0 : opts.split_min_degree;
     const float split_cost = work ? 0.f : opts.split_min_cost;
-    k_root_keys<<<gb, 256, 0, s>>>(n, roff, k, lcost, split_deg, split_cost, w.dbig, w.key, w.val, w.parts);
+    const int dbig_whole = opts.big_max_degree < 0 ? w.dbig : (opts.big_max_degree < w.dbig ? opts.big_max_degree : w.dbig);
+    k_root_keys<<<gs, 256, 0, s>>>(ns, roff, k, lcost, split_deg, split_cost, dbig_whole, opts.tier_fill, w.key,
+                                   w.val, w.parts);
     ARB_CHECK_LAUNCH();
-    if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, n, kCostBits + 3, w.radix_ws, s))) return rc;
-    k_sorted_units<<<gb, 256, 0, s>>>(n, roff, w.key, w.val, w.parts, w.ucnt);
+    if ((rc = radix_sort_u32(w.key, w.val, w.key_alt, w.val_alt, ns, kCostBits + 3, w.radix_ws, s))) return rc;
+    k_sorted_units<<<gs, 256, 0, s>>>(ns, roff, w.key, w.val, w.parts, w.ucnt);
     ARB_CHECK_LAUNCH();
-    if ((rc = exclusive_scan_i64(w.ucnt, w.ucnt, n, w.scan_ws, s))) return rc;
-    k_expand<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, roff, ridx, w.val, w.parts, w.ucnt,
-                                                         w.iroot, w.ichild);
+    if ((rc = exclusive_scan_i64(w.ucnt, w.ucnt, ns, w.scan_ws, s))) return rc;
+    k_expand<<<gs, 256, 0, s>>>(ns, roff, ridx, w.val, w.parts, w.ucnt, w.iroot, w.ichild);
     ARB_CHECK_LAUNCH();
-    k_segments<<<gb, 256, 0, s>>>(n, w.key, w.ucnt, w.seg);
+    k_segments<<<gs, 256, 0, s>>>(ns, w.key, w.ucnt, w.seg);
     ARB_CHECK_LAUNCH();
 
     const bool pvm = pv != nullptr;
@@ -464,7 +500,7 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
         ARB_HIP(hipStreamSynchronize(s));
     }
     const int cus = device_cus();
-    const bool prof = g_prof.enabled;
+    const bool prof = g_prof.enabled && !g_no_events;
     if (prof && g_prof.pending.size() > 2048 && (rc = prof_fold())) return rc;
     const bool conc = opts.concurrent_tiers && !plain;
     if (conc) {
@@ -488,11 +524,16 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
         a.pv = pv;
         a.per_root = per_root;
         a.work = work;
+        a.cycles = cycles;
+        a.root_ids = root_ids;
         a.err = w.err;
         a.chunk = t == 0 ? opts.chunk_small : 1;
         a.span_max = opts.bitmap_max_span;
         a.persistent = plain ? 0 : 1;
         a.one_item_per_team = plain ? 1 : 0;
+        a.ovf_items = w.big_teams > 0 ? w.ovf_items : nullptr;
+        a.ovf_count = w.ovf_count;
+        a.ovf_cap = w.ovf_cap;
         const int tpb = tier_teams_per_block(t);
         unsigned grid;
         if (plain) {
@@ -528,7 +569,8 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
         }
     }
     if (w.big_teams > 0) {
-        // roots above the LDS tiers, after the tier kernels (joined into s above)
+        // roots above the LDS tiers and overflowed pair items, after the tier kernels
+        // (joined into s above)
         CountArgs a;
         a.off = dg->offsets;
         a.idx = dg->indices;
@@ -545,11 +587,16 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
         a.pv = pv;
         a.per_root = per_root;
         a.work = work;
+        a.cycles = cycles;
+        a.root_ids = root_ids;
         a.err = w.err;
         a.chunk = 1;
         a.span_max = 0;
         a.persistent = 1;
         a.one_item_per_team = 0;
+        a.ovf_items = w.ovf_items;
+        a.ovf_count = w.ovf_count;
+        a.ovf_cap = w.ovf_cap;
         const BigArgs b{w.big_rows, w.big_words, w.dbig};
         const unsigned grid = (unsigned)(w.big_teams < cus ? w.big_teams : cus);
         ProfPending pp{ProfKey{kBigTier, k, pvm ? 1 : 0, instr ? 1 : 0}, nullptr, nullptr};
@@ -578,6 +625,23 @@ extern "C" int arb_count_async(const arb_ocsr *dg, int k, uint64_t *total_dev, u
                                uint64_t *per_root, uint64_t *work_out, const arb_count_opts *opts, void *ws,
                                size_t ws_bytes, void *stream) {
     int rc = count_impl(dg, k, total_dev, per_vertex, per_root, work_out, opts, ws, ws_bytes, as_stream(stream));
+    set_error(rc);
+    return rc;
+}
+
+extern "C" int arb_count_instrumented(const arb_ocsr *dg, int k, uint64_t *work_out, uint64_t *cycles_out,
+                                      const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+    int rc = ARB_OK;
+    if (!work_out || !ws) rc = ARB_EINVAL;
+    else if (ws_bytes < 64) rc = ARB_EWORKSPACE;
+    if (!rc) {
+        // the total goes to the workspace's own slot (the workspace is sized with room for it)
+        Carver cv(ws);
+        CountWs w;
+        carve_count(cv, dg && dg->n >= 0 ? dg->n : 0, dg && dg->m >= 0 ? dg->m : 0, k, &w);
+        rc = count_with_roots(dg, k, reinterpret_cast<uint64_t *>(w.tot), nullptr, nullptr, work_out, opts, ws,
+                              ws_bytes, as_stream(stream), nullptr, nullptr, 0, cycles_out);
+    }
     set_error(rc);
     return rc;
 }
@@ -656,9 +720,31 @@ struct TuneSpace {
     std::vector<int> blocks{2, 4, 8};
     std::vector<int> chunk{4, 16, 64};
     std::vector<int> span{0, 1 << 30};
+    std::vector<int> fill{100, 75, 50};
+    std::vector<int> bigmax{-1, 768};
 };
 
 }  // namespace
+
+extern "C" int arb_autotune_space(int dim, int max_values, double *values) {
+    TuneSpace sp;
+    std::vector<double> v;
+    switch (dim) {
+        case ARB_TUNE_SPLIT_MIN_DEGREE: v.assign(sp.split_deg.begin(), sp.split_deg.end()); break;
+        case ARB_TUNE_SPLIT_MIN_COST: v.assign(sp.split_cost.begin(), sp.split_cost.end()); break;
+        case ARB_TUNE_BLOCKS_PER_CU: v.assign(sp.blocks.begin(), sp.blocks.end()); break;
+        case ARB_TUNE_CHUNK_SMALL: v.assign(sp.chunk.begin(), sp.chunk.end()); break;
+        case ARB_TUNE_BITMAP_MAX_SPAN: v.assign(sp.span.begin(), sp.span.end()); break;
+        case ARB_TUNE_CONCURRENT_TIERS: v.assign(sp.conc.begin(), sp.conc.end()); break;
+        case ARB_TUNE_TIER_FILL: v.assign(sp.fill.begin(), sp.fill.end()); break;
+        case ARB_TUNE_BIG_MAX_DEGREE: v.assign(sp.bigmax.begin(), sp.bigmax.end()); break;
+        default: set_error(ARB_EINVAL); return -1;
+    }
+    if (max_values < 0 || (max_values > 0 && !values)) { set_error(ARB_EINVAL); return -1; }
+    for (int i = 0; i < (int)v.size() && i < max_values; ++i) values[i] = v[i];
+    set_error(ARB_OK);
+    return (int)v.size();
+}
 
 extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int trials, float *best_ms,
                             void *ws, size_t ws_bytes, void *stream) {
@@ -675,7 +761,10 @@ extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int
     uint64_t ref_total = 0;
     bool have_ref = false;
     int rc = ARB_OK;
-    // time one configuration: one warm-up, then the best of `trials`; totals must agree
+    // time one configuration: one warm-up, then the best of `trials`; totals must agree.
+    // A candidate whose warm-up run takes more than twice the best time so far is not
+    // timed further (its time is the warm-up's)
+    float cur_ms = 0.f;
     auto measure = [&](const arb_count_opts &o, float *ms_out) -> int {
         float best = 1e30f;
         for (int t = 0; t <= trials; ++t) {
@@ -686,6 +775,10 @@ extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return ARB_EHIP;
             if (t > 0 && ms < best) best = ms;
+            if (t == 0 && have_ref && ms > 2.f * cur_ms) {
+                best = ms;
+                break;
+            }
         }
         uint64_t h = 0;
         if (hipMemcpy(&h, tot, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return ARB_EHIP;
@@ -699,13 +792,13 @@ extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int
     arb_count_opts cur = *opts;
     if (cur.schedule == ARB_SCHED_PLAIN) cur.schedule = ARB_SCHED_PERSISTENT;
     const bool learned = cur.schedule == ARB_SCHED_LEARNED;
-    float cur_ms = 0.f;
     if ((rc = measure(cur, &cur_ms))) goto out;
     for (int pass = 0; pass < 2; ++pass) {
-        for (int param = 0; param < 5; ++param) {
+        for (int param = 0; param < 7; ++param) {
             const int nv = param == 0 ? (learned ? (int)sp.split_cost.size() : (int)sp.split_deg.size())
                          : param == 1 ? (int)sp.blocks.size() : param == 2 ? (int)sp.chunk.size()
-                         : param == 3 ? (int)sp.span.size() : (int)sp.conc.size();
+                         : param == 3 ? (int)sp.span.size() : param == 4 ? (int)sp.conc.size()
+                         : param == 5 ? (int)sp.fill.size() : (int)sp.bigmax.size();
             for (int i = 0; i < nv; ++i) {
                 arb_count_opts o = cur;
                 if (param == 0) {
@@ -714,7 +807,9 @@ extern "C" int arb_autotune(const arb_ocsr *dg, int k, arb_count_opts *opts, int
                 } else if (param == 1) o.persist_blocks_per_cu = sp.blocks[i];
                 else if (param == 2) o.chunk_small = sp.chunk[i];
                 else if (param == 3) o.bitmap_max_span = sp.span[i];
-                else o.concurrent_tiers = sp.conc[i];
+                else if (param == 4) o.concurrent_tiers = sp.conc[i];
+                else if (param == 5) o.tier_fill = sp.fill[i];
+                else o.big_max_degree = sp.bigmax[i];
                 if (memcmp(&o, &cur, sizeof(o)) == 0) continue;
                 float ms = 0.f;
                 if ((rc = measure(o, &ms))) goto out;

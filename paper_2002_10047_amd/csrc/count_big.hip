@@ -1,16 +1,28 @@
-// Counting for roots whose out-neighbourhood exceeds the largest LDS tier (k = 3, 4):
-// Alg. 1 at the root as in the tiers (Sec. 3.2, 3.4), with G[N+(v)] as upper-triangular
-// bit rows in a per-team slice of global scratch instead of LDS.  One 16-wave team per
-// root; S = N+(v) and an LDS hash from id to local id serve the second level (the
-// gathered N+(u) lists set bits with global atomics); at k = 4 the pairs (x, y) of G[S]
-// go through per-wave rings to the lanes, each adding popcount(row x AND row y) over the
-// words at or above y's word.  Per-vertex counts as in the tiers: a pair's common upper
-// neighbours z each gain 1 and x, y gain their number.
+// Counting for work items whose candidate set exceeds the largest LDS tier: Alg. 1 at the
+// item as in the tiers (Sec. 3.2, 3.4), with G[S] as bit rows in a per-team slice of
+// global scratch (L2 / Infinity Cache resident) instead of LDS.  Items are whole roots
+// with ARB_MAX_LOCAL < d+ <= dbig (from the schedule), and (root, child) pair items whose
+// set N+(root) ∩ N+(child) overflowed the largest LDS tier (appended to an overflow list
+// by the tier kernels, which run before this kernel).  One 16-wave team per item:
+//   * S and an LDS hash from id to local id serve the second level; the gathered N+(u)
+//     lists set row bits with global atomics (upper rows: row x = x's neighbours above x;
+//     symmetric rows in the per-vertex mode);
+//   * the pair phase is wave-cooperative: a wave claims a row x and holds it across its
+//     lanes (lane l: words l and l + 64, rows of up to 4096 bits), then for each member y
+//     of the row it reads row y with one coalesced load per lane and forms
+//     J = row x AND row y above y;
+//   * k - 1 = 3 (k = 4 roots, k = 5 pairs): each lane adds the popcount of its words of
+//     J; deeper: a walk over J in which every set is held across the lanes the same way
+//     (members taken in ascending order with a ballot; frames of a private stack for the
+//     levels above the last), each node costing one coalesced row read.
+// Per-vertex counts as in the tiers: at a node needing two more vertices with set I, each
+// z in I gains popcount(I AND adj(z)), the chosen vertices gain the node's cliques.
 #include "count_kernels.h"
 
 namespace arb {
 
 constexpr int kBigGatherUnroll = 8;   // independent 4-byte list loads in flight per lane
+constexpr int kWaveFrames = ARB_MAX_K - 4;
 
 template <bool PV>
 struct BigLds {
@@ -18,27 +30,23 @@ struct BigLds {
     static constexpr int HS = 2 * kBigMax;
     static constexpr int HB = 13;
     static constexpr int SPAN = 0;          // membership always through the hash
-    static constexpr int RING = 128;        // per-wave pair ring, rows written in windows
     int32_t S[kBigMax];
     unsigned long long H[HS];
     unsigned long long cnt[PV ? kBigMax : 1];
-    union {
-        uint32_t ring[TW][RING];
-        ListEnt lt[TW][64];
-    } q;
+    ListEnt lt[TW][64];
     unsigned long long red[TW];
     int d;
     int pop;
     int next;
 };
 static_assert((1 << BigLds<true>::HB) == BigLds<true>::HS, "hash size");
-static_assert(sizeof(BigLds<true>) <= 160 * 1024, "big-root LDS");
+static_assert(sizeof(BigLds<true>) <= 160 * 1024, "big-item LDS");
 
-// second level of a big root: lists N+(S[i]) for i = wv, wv + 16, ... as one stream per wave
-template <bool PV, class Lds>
+// second level: lists N+(S[i]) for i = wv, wv + 16, ... as one stream per wave
+template <bool PV, bool SYM, class Lds>
 __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int32_t first, int32_t last, int wv,
                            int lane, uint32_t *grow, int W, unsigned long long &mine, unsigned long long &words) {
-    AS3<ListEnt> *lt = T->q.lt[wv];
+    AS3<ListEnt> *lt = T->lt[wv];
     const int nl = wv < d ? (d - wv + Lds::TW - 1) / Lds::TW : 0;
     for (int gb = 0; gb < nl; gb += 64) {
         const int t = gb + lane;
@@ -99,6 +107,7 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int
                     }
                 } else {
                     atomicOr(&grow[(int64_t)i * W + (j >> 5)], 1u << (j & 31));
+                    if constexpr (SYM) atomicOr(&grow[(int64_t)j * W + (i >> 5)], 1u << (i & 31));
                 }
             }
         }
@@ -106,31 +115,125 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int
     }
 }
 
-// popcount(row x AND row y) over the words at or above y's word; per-vertex: each common
-// upper neighbour z gains 1
-template <bool PV, class Lds>
-__device__ __forceinline__ unsigned big_pair(AS3<Lds> *T, const uint32_t *grow, int W, int x, int y) {
-    const uint32_t *rx = grow + (int64_t)x * W;
-    const uint32_t *ry = grow + (int64_t)y * W;
-    unsigned c = 0;
-    for (int w = y >> 5; w < W; ++w) {
-        uint32_t t = rx[w] & ry[w];
-        c += __popc(t);
-        if constexpr (PV) {
-            while (t) {
-                const int b = __ffs(t) - 1;
-                t &= t - 1;
-                lds_add(&T->cnt[w * 32 + b], 1ull);
-            }
-        }
+// A set of local ids held across the wave: lane l keeps words l (h0) and l + 64 (h1).
+struct WSet {
+    uint32_t h0, h1;
+};
+
+__device__ __forceinline__ WSet wload(const uint32_t *row, int W, int lane) {
+    WSet r;
+    r.h0 = lane < W ? row[lane] : 0u;
+    r.h1 = lane + 64 < W ? row[lane + 64] : 0u;
+    return r;
+}
+
+__device__ __forceinline__ WSet wand(WSet a, WSet b) { return WSet{a.h0 & b.h0, a.h1 & b.h1}; }
+
+// members above z (bits of the lane's words that stand for ids > z)
+__device__ __forceinline__ WSet wabove(WSet a, int z, int lane) {
+    return WSet{a.h0 & gtmask(z, lane), a.h1 & gtmask(z, lane + 64)};
+}
+
+__device__ __forceinline__ unsigned wpopc(WSet a) { return (unsigned)(__popc(a.h0) + __popc(a.h1)); }
+
+// lowest member of the wave's set, removed from it; -1 when empty (wave-uniform)
+__device__ __forceinline__ int wpop(WSet &a, int lane) {
+    uint64_t m = __ballot(a.h0 != 0u);
+    int base = 0;
+    uint32_t word;
+    int src;
+    if (m) {
+        src = __ffsll((unsigned long long)m) - 1;
+        word = __shfl(a.h0, src, 64);
+    } else {
+        m = __ballot(a.h1 != 0u);
+        if (!m) return -1;
+        src = __ffsll((unsigned long long)m) - 1;
+        word = __shfl(a.h1, src, 64);
+        base = 64;
     }
-    if constexpr (PV) {
-        if (c) {
-            lds_add(&T->cnt[x], (unsigned long long)c);
-            lds_add(&T->cnt[y], (unsigned long long)c);
+    const int z = (base + src) * 32 + __ffs(word) - 1;
+    if (lane == src) {
+        if (base == 0) a.h0 &= a.h0 - 1;
+        else a.h1 &= a.h1 - 1;
+    }
+    return z;
+}
+
+__device__ __forceinline__ bool wempty(WSet a) { return __ballot((a.h0 | a.h1) != 0u) == 0; }
+
+// per-vertex credit at a node needing two more vertices with set I: each z in I gains its
+// neighbours in I (symmetric rows); returns the lane's share of the node's cliques
+template <bool PV, bool INSTR, class Lds>
+__device__ __forceinline__ unsigned long long wleaf(AS3<Lds> *T, const uint32_t *grow, int W, WSet I, int lane,
+                                                    unsigned long long &nodes) {
+    if constexpr (INSTR) nodes += wpopc(I);
+    unsigned long long c = 0;
+    WSet R = I;
+    while (true) {
+        const int z = wpop(R, lane);
+        if (z < 0) break;
+        const WSet rz = wload(grow + (int64_t)z * W, W, lane);
+        c += wpopc(wand(R, rz));                          // R: I's members above z
+        if constexpr (PV) {
+            const unsigned long long az = wave_sum((unsigned long long)wpopc(wand(I, rz)));
+            if (lane == 0 && az) lds_add(&T->cnt[z], az);
         }
     }
     return c;
+}
+
+// L-cliques (L >= 2) inside the wave's set J: frames of a private stack hold the untaken
+// members of every level above the last two; returns the lane's share
+template <bool PV, bool INSTR, class Lds>
+__device__ __attribute__((noinline)) unsigned long long wdfs(AS3<Lds> *T, const uint32_t *grow, int W, WSet J,
+                                                              int L, int lane, unsigned long long *nodes_out) {
+    unsigned long long nodes = 0;
+    if (L == 2) {
+        const unsigned long long c = wleaf<PV, INSTR, Lds>(T, grow, W, J, lane, nodes);
+        if constexpr (INSTR) *nodes_out += nodes;
+        return c;
+    }
+    WSet R[kWaveFrames];
+    int Z[kWaveFrames];
+    unsigned long long C[kWaveFrames];
+    int f = 0;
+    R[0] = J;
+    C[0] = 0;
+    if constexpr (INSTR) nodes += wpopc(J);
+    while (true) {
+        const int z = wpop(R[f], lane);
+        if (z < 0) {
+            if (f == 0) break;
+            const unsigned long long c = C[f];
+            --f;
+            if constexpr (PV) {
+                const unsigned long long t = wave_sum(c);
+                if (lane == 0 && t) lds_add(&T->cnt[Z[f]], t);
+            }
+            C[f] += c;
+            continue;
+        }
+        const WSet K = wand(R[f], wload(grow + (int64_t)z * W, W, lane));   // R: members above z
+        const int lvl = L - f;                  // vertices to choose in frame f, z included
+        if (wempty(K)) continue;
+        if (lvl == 3) {
+            const unsigned long long c = wleaf<PV, INSTR, Lds>(T, grow, W, K, lane, nodes);
+            if constexpr (PV) {
+                const unsigned long long t = wave_sum(c);
+                if (lane == 0 && t) lds_add(&T->cnt[z], t);
+            }
+            C[f] += c;
+        } else {
+            if constexpr (INSTR) nodes += wpopc(K);
+            Z[f] = z;
+            ++f;
+            R[f] = K;
+            C[f] = 0;
+        }
+    }
+    if constexpr (INSTR) *nodes_out += nodes;
+    return C[0];
 }
 
 template <bool PV, bool INSTR>
@@ -140,29 +243,83 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];
     AS3<Lds> *T = (AS3<Lds> *)smem;
     const int tlid = threadIdx.x, lane = tlid & 63, wv = tlid >> 6;
+    const uint64_t below = lanes_below_mask();
     uint32_t *grow = b.rows + (int64_t)blockIdx.x * b.team_words;
     const int64_t beg = a.seg[0], end = a.seg[1];
+    const int64_t nseg = end - beg;
     unsigned long long acc = 0;
     while (true) {
         __syncthreads();
         if (tlid == 0) T->pop = atomicAdd(a.head, 1);
         __syncthreads();
-        const int64_t it = beg + (int64_t)T->pop;
-        if (it >= end) break;
+        // schedule items first, then the overflowed pair items of the tier kernels
+        const int64_t q = (int64_t)T->pop;
+        int64_t it;
+        if (q < nseg) {
+            it = beg + q;
+        } else {
+            const int64_t o = q - nseg;
+            const int64_t novf = (int64_t)*a.ovf_count;
+            if (o >= (novf < a.ovf_cap ? novf : a.ovf_cap)) break;
+            it = a.ovf_items[o];
+        }
         const int32_t root = a.item_root[it];
-        const int64_t s0 = a.roff[root];
-        const int64_t d64 = a.roff[root + 1] - s0;
-        if (d64 > b.dbig || d64 > kBigMax || a.item_child[it] != -1) {
-            if (tlid == 0) atomicOr(a.err, 1);
+        const int32_t child = a.item_child[it];
+        const unsigned long long t_start = INSTR ? (unsigned long long)clock64() : 0ull;
+        int need;
+        if (child == -1) {
+            const int64_t s0 = a.roff[root];
+            const int64_t d64 = a.roff[root + 1] - s0;
+            if (d64 > b.dbig) {
+                if (tlid == 0) atomicOr(a.err, 1);
+                continue;
+            }
+            for (int i = tlid; i < (int)d64; i += TT) T->S[i] = a.ridx[s0 + i];
+            if (tlid == 0) T->d = (int)d64;
+            need = a.k - 1;
+        } else if (child >= 0) {
+            // S = N+(root) ∩ N+(child): wave 0 walks N+(child), binary-searching N+(root)
+            if (wv == 0) {
+                const int64_t rs = a.roff[root], re = a.roff[root + 1];
+                const int64_t cs = a.off[child], ce = a.off[child + 1];
+                int cntS = 0;
+                for (int64_t p0 = cs; p0 < ce; p0 += 64) {
+                    const int64_t p = p0 + lane;
+                    bool hit = false;
+                    int32_t w = 0;
+                    if (p < ce) {
+                        w = a.idx[p];
+                        int64_t lo = rs, hi = re;
+                        while (lo < hi) {
+                            const int64_t mid = lo + ((hi - lo) >> 1);
+                            if (a.ridx[mid] < w) lo = mid + 1; else hi = mid;
+                        }
+                        hit = lo < re && a.ridx[lo] == w;
+                    }
+                    const uint64_t m = __ballot(hit);
+                    const int pos = cntS + __popcll(m & below);
+                    if (hit && pos < b.dbig) T->S[pos] = w;
+                    cntS += __popcll(m);
+                }
+                if (cntS > b.dbig) {
+                    if (lane == 0) atomicOr(a.err, 1);
+                    cntS = 0;
+                }
+                if (lane == 0) T->d = cntS;
+            }
+            need = a.k - 2;
+        } else {
+            if (tlid == 0) atomicOr(a.err, 1);     // split parts never come here
             continue;
         }
-        const int d = (int)d64, W = (d + 31) / 32;
-        const int need = a.k - 1;                       // 2 or 3
-        for (int i = tlid; i < d; i += TT) T->S[i] = a.ridx[s0 + i];
+        __syncthreads();
+        const int d = T->d;
+        if (d < need || d == 0) continue;          // no clique fits
+        const int W = (d + 31) / 32;
         for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
         if constexpr (PV)
             for (int i = tlid; i < d; i += TT) T->cnt[i] = 0ull;
-        if (need == 3)
+        if (need >= 3)
             for (int64_t i = tlid; i < (int64_t)d * W; i += TT) grow[i] = 0u;
         if (tlid == 0) T->next = TW;
         // the zeroed rows must reach L2 before any wave's atomics
@@ -172,75 +329,83 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
         __syncthreads();
         const int32_t first = T->S[0], last = T->S[d - 1];
         unsigned long long mine = 0, words = 0, nodes = 0;
-        big_gather<PV, Lds>(T, a, d, need, first, last, wv, lane, grow, W, mine, words);
-        if (need == 3) {
+        if (need == 1) {
+            if (tlid == 0) mine = (unsigned long long)d;
+            if constexpr (PV)
+                for (int i = tlid; i < d; i += TT) T->cnt[i] = 1ull;
+        } else {
+            big_gather<PV, PV, Lds>(T, a, d, need, first, last, wv, lane, grow, W, mine, words);
+        }
+        if (need >= 3) {
             // the rows were set by global atomics of all waves: complete them, then read
             // them past this CU's L1
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            AS3<uint32_t> *ring = T->q.ring[wv];
-            unsigned head = 0, tail = 0;
+            const int pneed = need - 2;
             int x = wv;
             while (x < d) {
-                const uint32_t *rx = grow + (int64_t)x * W;
-                for (int cw = 0; cw < W; cw += 64) {
-                    uint32_t bits = cw + lane < W ? rx[cw + lane] : 0u;
-                    const unsigned c = __popc(bits);
-                    unsigned pre = c;
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const unsigned y = __shfl_up(pre, o, 64);
-                        if (lane >= o) pre += y;
-                    }
-                    const unsigned stop_all = tail + __shfl(pre, 63, 64);
-                    unsigned pos = tail + pre - c;
-                    while (true) {
-                        while (bits && pos - head < (unsigned)Lds::RING) {
-                            const int bb = __ffs(bits) - 1;
-                            bits &= bits - 1;
-                            ring[pos & (Lds::RING - 1)] = ((uint32_t)x << 16) | (uint32_t)((cw + lane) * 32 + bb);
-                            ++pos;
+                WSet rx = wload(grow + (int64_t)x * W, W, lane);
+                if constexpr (PV) rx = wabove(rx, x, lane);       // symmetric rows: members above x
+                WSet Y = rx;
+                unsigned long long cx = 0;                         // per-vertex: cliques through x
+                while (true) {
+                    const int y = wpop(Y, lane);
+                    if (y < 0) break;
+                    if constexpr (INSTR) nodes += lane == 0 ? 1ull : 0ull;
+                    WSet ry = wload(grow + (int64_t)y * W, W, lane);
+                    const WSet J = PV ? wabove(wand(rx, ry), y, lane) : wand(rx, ry);
+                    unsigned long long c;
+                    if (pneed == 1) {
+                        c = wpopc(J);
+                        if constexpr (PV) {
+                            uint32_t t0 = J.h0, t1 = J.h1;
+                            while (t0) {
+                                lds_add(&T->cnt[lane * 32 + __ffs(t0) - 1], 1ull);
+                                t0 &= t0 - 1;
+                            }
+                            while (t1) {
+                                lds_add(&T->cnt[(lane + 64) * 32 + __ffs(t1) - 1], 1ull);
+                                t1 &= t1 - 1;
+                            }
                         }
-                        wave_fence();
-                        const bool all = stop_all - head <= (unsigned)Lds::RING;
-                        const unsigned stop = all ? stop_all : head + Lds::RING;
-                        while (stop - head >= 64) {
-                            const uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                            mine += big_pair<PV, Lds>(T, grow, W, (int)(p >> 16), (int)(p & 0xffffu));
-                            if constexpr (INSTR) nodes += 1;
-                            head += 64;
-                        }
-                        wave_fence();
-                        if (all) break;
+                    } else {
+                        c = wdfs<PV, INSTR, Lds>(T, grow, W, J, pneed, lane, &nodes);
                     }
-                    tail = stop_all;
+                    mine += c;
+                    if constexpr (PV) {
+                        const unsigned long long t = wave_sum(c);
+                        if (lane == 0 && t) lds_add(&T->cnt[y], t);
+                        cx += t;
+                    }
+                }
+                if constexpr (PV) {
+                    if (lane == 0 && cx) lds_add(&T->cnt[x], cx);
                 }
                 int nx = 0;
                 if (lane == 0) nx = __hip_atomic_fetch_add(&T->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 x = __shfl(nx, 0, 64);
             }
-            if (tail != head && lane < (int)(tail - head)) {
-                const uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                mine += big_pair<PV, Lds>(T, grow, W, (int)(p >> 16), (int)(p & 0xffffu));
-                if constexpr (INSTR) nodes += 1;
-            }
         }
         const unsigned long long item = team_sum<TW, 1>(T, mine, wv, lane);
-        if (a.per_root != nullptr && tlid == 0 && item) atomicAdd(&a.per_root[root], item);
+        const int32_t rv = a.root_ids ? a.root_ids[root] : root;     // the root vertex
+        if (a.per_root != nullptr && tlid == 0 && item) atomicAdd(&a.per_root[rv], item);
         if constexpr (PV) {
             for (int i = tlid; i < d; i += TT) {
                 const unsigned long long c = T->cnt[i];
                 if (c) atomicAdd(&a.pv[T->S[i]], c);
             }
-            if (tlid == 0 && item) atomicAdd(&a.pv[root], item);
+            if (tlid == 0 && item) {
+                atomicAdd(&a.pv[rv], item);
+                if (child >= 0) atomicAdd(&a.pv[child], item);
+            }
         }
         if constexpr (INSTR) {
-            // work label: gathered words + ceil(d/32) per search-tree node (d at depth 1,
-            // the pairs at depth 2 when k = 4)
+            // work label: gathered words + ceil(d/32) per search-tree node (d at depth 1)
             const unsigned long long tn = team_sum<TW, 1>(T, nodes, wv, lane);
             const unsigned long long tg = team_sum<TW, 1>(T, words, wv, lane);
-            if (tlid == 0) a.work[root] = tg + (unsigned long long)W * ((unsigned long long)d + tn);
+            if (tlid == 0 && child < 0) a.work[rv] = tg + (unsigned long long)W * ((unsigned long long)d + tn);
+            if (tlid == 0 && a.cycles) atomicAdd(&a.cycles[rv], (unsigned long long)clock64() - t_start);
         }
         acc += mine;
         // the next item clears and rewrites this team's rows

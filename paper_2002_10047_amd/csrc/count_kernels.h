@@ -297,11 +297,18 @@ struct CountArgs {
     unsigned long long *pv;        // nullable
     unsigned long long *per_root;  // nullable: cliques whose lowest-ranked vertex is the root
     unsigned long long *work;      // nullable
+    unsigned long long *cycles;    // nullable (instrumented): shader clock cycles per root
+    const int32_t *root_ids;       // nullable: item roots are positions in this list of vertices
     int32_t *err;
     int chunk;
     int span_max;                  // id-range bitmap used when the span is below this
     int persistent;
     int one_item_per_team;         // non-persistent launch: team g takes item begin + g
+    // pair items whose set overflows the largest LDS tier are listed here for the
+    // global-scratch kernel (null: no such kernel, the overflow is an error)
+    int64_t *ovf_items;
+    unsigned long long *ovf_count;
+    int64_t ovf_cap;
 };
 
 // ------------------------------------------------------------------ subtree walk
@@ -428,6 +435,78 @@ __device__ __attribute__((noinline)) Acc dfs_body(AS3<Lds> *T, Bits<W> J) {
     return dfs_inline<W, PV, INSTR, L, Lds>(T, J);
 }
 
+// Walks with more than 7 vertices still to choose (k > 10): the levels down to the fourth
+// keep their untaken candidates in a stack of frames in private memory instead of in the
+// registers of nested calls, so that one function serves every depth up to ARB_MAX_K - 3;
+// the last three levels run inline.  Frame f holds the set from which L - f vertices are
+// still to be chosen.  Without instrumentation a frame whose set has fewer members than
+// vertices to choose is not entered (it holds no clique).
+constexpr int kDeepFrames = ARB_MAX_K - 6;
+constexpr int kDeepMin = 8;
+
+template <int W, bool PV, bool INSTR, class Lds>
+__device__ __attribute__((noinline)) Acc dfs_deep(AS3<Lds> *T, Bits<W> J, int L) {
+    uint32_t R[kDeepFrames][W];
+    int Z[kDeepFrames];
+    unsigned long long C[kDeepFrames], N[kDeepFrames];
+    int f = 0;
+    unsigned pc0 = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        R[0][w] = J.w[w];
+        pc0 += __popc(J.w[w]);
+    }
+    C[0] = 0;
+    N[0] = INSTR ? pc0 : 0;
+    while (true) {
+        int z = -1;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (z < 0 && R[f][w]) {
+                z = w * 32 + __ffs(R[f][w]) - 1;
+                R[f][w] &= R[f][w] - 1;
+            }
+        }
+        if (z < 0) {                       // frame f done: credit the parent's chosen vertex
+            if (f == 0) return Acc{C[0], N[0]};
+            const unsigned long long c = C[f], nn = N[f];
+            --f;
+            if constexpr (PV) {
+                if (c) lds_add(&T->cnt[Z[f]], c);
+            }
+            C[f] += c;
+            N[f] += nn;
+            continue;
+        }
+        uint32_t rz[W];
+        load_row<W, 0, Lds>(T, z, rz);
+        Bits<W> K;
+        unsigned pc = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            K.w[w] = R[f][w] & rz[w];      // R: the frame's members above z
+            pc += __popc(K.w[w]);
+        }
+        const int lvl = L - f;             // vertices to choose in frame f, z included
+        if (lvl == 4) {
+            const Acc sub = dfs_inline<W, PV, INSTR, 3, Lds>(T, K);
+            if constexpr (PV) {
+                if (sub.c) lds_add(&T->cnt[z], sub.c);
+            }
+            C[f] += sub.c;
+            N[f] += sub.nodes;
+        } else {
+            if (!INSTR && pc < (unsigned)(lvl - 1)) continue;
+            Z[f] = z;
+            ++f;
+#pragma unroll
+            for (int w = 0; w < W; ++w) R[f][w] = K.w[w];
+            C[f] = 0;
+            N[f] = INSTR ? pc : 0;
+        }
+    }
+}
+
 template <int W, int LMAX, bool PV, bool INSTR, class Lds>
 __device__ __forceinline__ Acc dfs_dispatch(AS3<Lds> *T, const Bits<W> &J, int L) {
     if constexpr (LMAX >= 2) if (L == 2) return dfs_inline<W, PV, INSTR, 2, Lds>(T, J);
@@ -436,9 +515,10 @@ __device__ __forceinline__ Acc dfs_dispatch(AS3<Lds> *T, const Bits<W> &J, int L
     if constexpr (LMAX >= 5) if (L == 5) return dfs_body<W, PV, INSTR, 5, Lds>(T, J);
     if constexpr (LMAX >= 6) if (L == 6) return dfs_body<W, PV, INSTR, 6, Lds>(T, J);
     if constexpr (LMAX >= 7) if (L == 7) return dfs_body<W, PV, INSTR, 7, Lds>(T, J);
+    if constexpr (LMAX >= kDeepMin) if (L >= kDeepMin) return dfs_deep<W, PV, INSTR, Lds>(T, J, L);
     return Acc{0ull, 0ull};
 }
-static_assert(ARB_MAX_K - 3 <= 7, "dfs_dispatch covers L up to ARB_MAX_K - 3");
+static_assert(ARB_MAX_K - 3 - kDeepMin + 4 <= kDeepFrames, "dfs_deep's frames cover L up to ARB_MAX_K - 3");
 
 // One pair (x, y) of the induced subgraph, x < y, both chosen: count the cliques that
 // extend it with `need` more vertices from S (need >= 1); .nodes as in dfs.
@@ -586,7 +666,7 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
 
 template <int W, int LMAX, bool PV, bool INSTR>
 __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, TierCfg<W, PV, LMAX>::TW>> *T,
-                                                             const CountArgs a, int32_t root,
+                                                             const CountArgs a, int64_t it, int32_t root,
                                                              int32_t child, int tlid) {
     using Cfg = TierCfg<W, PV, LMAX>;
     constexpr int TW = Cfg::TW, TPB = Cfg::TPB;
@@ -596,6 +676,7 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     const uint64_t below = lanes_below_mask();
 
     team_sync<TW, TPB>();            // previous item finished with the LDS
+    const unsigned long long t_start = INSTR ? (unsigned long long)clock64() : 0ull;
     // child >= 0: the pair item (root, child); child == -1: the whole root; child <= -2:
     // part `part` of P of a split root, which takes every P-th row of the root's work
     int P = 1, part = 0;
@@ -640,7 +721,12 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
                 cntS += __popcll(m);
             }
             if (cntS > Lds::D) {
-                if (lane == 0) atomicOr(a.err, 1);
+                // too large for LDS: the global-scratch kernel (run after the tiers) takes it
+                if (lane == 0) {
+                    const unsigned long long o = a.ovf_items ? atomicAdd(a.ovf_count, 1ull) : ~0ull;
+                    if (o < (unsigned long long)a.ovf_cap) a.ovf_items[o] = it;
+                    else atomicOr(a.err, 1);
+                }
                 cntS = 0;
             }
             if (lane == 0) T->d = cntS;
@@ -798,8 +884,9 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     }
 
     unsigned long long item = 0;
+    const int32_t rv = a.root_ids ? a.root_ids[root] : root;     // the root vertex
     if (PV || a.per_root != nullptr) item = team_sum<TW, TPB>(T, mine, wv, lane);
-    if (a.per_root != nullptr && tlid == 0 && item) atomicAdd(&a.per_root[root], item);
+    if (a.per_root != nullptr && tlid == 0 && item) atomicAdd(&a.per_root[rv], item);
     if constexpr (PV || INSTR) {
         if constexpr (PV) {
             for (int i = tlid; i < d; i += TT) {
@@ -807,14 +894,15 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
                 if (c) atomicAdd(&a.pv[T->S[i]], c);
             }
             if (tlid == 0 && item) {
-                atomicAdd(&a.pv[root], item);
+                atomicAdd(&a.pv[rv], item);
                 if (child >= 0) atomicAdd(&a.pv[child], item);
             }
         }
         if constexpr (INSTR) {
             const unsigned long long tn = team_sum<TW, TPB>(T, nodes, wv, lane);
             const unsigned long long tg = team_sum<TW, TPB>(T, gather, wv, lane);
-            if (tlid == 0 && child < 0) a.work[root] = tg + (unsigned long long)((d + 31) / 32) * tn;
+            if (tlid == 0 && child < 0) a.work[rv] = tg + (unsigned long long)((d + 31) / 32) * tn;
+            if (tlid == 0 && a.cycles) atomicAdd(&a.cycles[rv], (unsigned long long)clock64() - t_start);
         }
     }
     return mine;
@@ -843,11 +931,11 @@ k_count(CountArgs a) {
     const int64_t gteam = (int64_t)blockIdx.x * TPB + team;
     if (a.one_item_per_team) {
         int64_t it = beg + gteam;
-        if (it < end) acc += process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid);
+        if (it < end) acc += process_item<W, LMAX, PV, INSTR>(T, a, it, a.item_root[it], a.item_child[it], tlid);
     } else if (!a.persistent) {
         const int64_t nteams = (int64_t)gridDim.x * TPB;
         for (int64_t it = beg + gteam; it < end; it += nteams)
-            acc += process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid);
+            acc += process_item<W, LMAX, PV, INSTR>(T, a, it, a.item_root[it], a.item_child[it], tlid);
     } else {
         while (true) {
             team_sync<TW, TPB>();
@@ -857,7 +945,7 @@ k_count(CountArgs a) {
             if (first >= end) break;
             const int64_t last = min(first + (int64_t)a.chunk, end);
             for (int64_t it = first; it < last; ++it)
-                acc += process_item<W, LMAX, PV, INSTR>(T, a, a.item_root[it], a.item_child[it], tlid);
+                acc += process_item<W, LMAX, PV, INSTR>(T, a, it, a.item_root[it], a.item_child[it], tlid);
         }
     }
     acc = wave_sum(acc);
@@ -873,7 +961,7 @@ constexpr size_t block_lds() {
 template <int W>
 constexpr bool tier_fits_lds() {
     return block_lds<W, true, 1>() <= 160 * 1024 && block_lds<W, false, 1>() <= 160 * 1024 &&
-           block_lds<W, true, 7>() <= 160 * 1024 && block_lds<W, false, 7>() <= 160 * 1024;
+           block_lds<W, true, kDeepMin>() <= 160 * 1024 && block_lds<W, false, kDeepMin>() <= 160 * 1024;
 }
 static_assert(tier_fits_lds<2>() && tier_fits_lds<4>() && tier_fits_lds<8>() && tier_fits_lds<12>() &&
                   tier_fits_lds<16>() && tier_fits_lds<24>(), "a tier's block exceeds the CU's LDS");
@@ -936,14 +1024,15 @@ inline size_t tier_block_lds(int tier, bool pv, int lmax) {
     }
 }
 
-// Roots with more than ARB_MAX_LOCAL out-neighbours at k = 3, 4 (count_big.hip): one
-// 16-wave team per root, S and its hash in LDS, the bit rows of G[S] in a per-team slice
-// of global scratch (L2-resident), up to kBigMax out-neighbours.
+// Items whose candidate set exceeds ARB_MAX_LOCAL (count_big.hip): one 16-wave team per
+// item, S and its hash in LDS, the bit rows of G[S] in a per-team slice of global scratch
+// (L2 / Infinity Cache resident), up to kBigMax vertices.
 constexpr int kBigMax = 4096;
 struct BigArgs {
     uint32_t *rows;        // scratch: teams x team_words words
     int64_t team_words;
-    int dbig;              // roots with ARB_MAX_LOCAL < d+ <= dbig take this path
+    int dbig;              // roots with ARB_MAX_LOCAL < d+ <= dbig and overflowed pair
+                           // sets up to dbig take this path
 };
 
 // Largest out-degree the peel can produce on m edges: d(d+1) <= 2(2+eps)m, so at eps = 1
@@ -966,7 +1055,8 @@ int launch_count_big(bool pv, bool instr, const CountArgs &a, const BigArgs &b, 
 // count.hip: the counting driver with optional per-root candidate sets (see there)
 int count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex, uint64_t *per_root_out,
                      uint64_t *work_out, const arb_count_opts *opts_in, void *ws, size_t ws_bytes, hipStream_t s,
-                     const int64_t *roff, const int32_t *ridx, int64_t rnnz);
+                     const int64_t *roff, const int32_t *ridx, int64_t rnnz, uint64_t *cycles_out = nullptr,
+                     const int32_t *root_ids = nullptr, int64_t nroots = 0, bool pv_zeroed = false);
 
 #define ARB_DECLARE_DEPTH(LM) \
     int launch_count_depth##LM(int tier, bool pv, bool instr, const CountArgs &a, unsigned grid, hipStream_t s);
@@ -977,6 +1067,7 @@ ARB_DECLARE_DEPTH(4)
 ARB_DECLARE_DEPTH(5)
 ARB_DECLARE_DEPTH(6)
 ARB_DECLARE_DEPTH(7)
+ARB_DECLARE_DEPTH(8)
 #undef ARB_DECLARE_DEPTH
 
 }  // namespace arb

@@ -37,8 +37,9 @@ def tuned_opts(ooff, oidx, k, schedule, mlp_weights=None, features=None, ws=None
     if not retune and key in cache:
         e = cache[key]
         for f in ("split_min_degree", "split_min_cost", "persist_blocks_per_cu", "chunk_small", "bitmap_max_span",
-                  "concurrent_tiers"):
-            setattr(op, f, e[f])
+                  "concurrent_tiers", "tier_fill", "big_max_degree"):
+            if f in e:
+                setattr(op, f, e[f])
         return op, None
     ms = arb.arb_autotune(ooff, oidx, k, op, trials=trials, ws=ws)
     e = arb.opts_dict(op)

@@ -100,6 +100,14 @@ def test_full_c2_per_vertex_sampled(arb, orc, c2, k):
     assert np.array_equal(pv[verts], ref)
 
 
+def csr_digest(off, idx) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    h.update(off.cpu().numpy().astype(np.int64).tobytes())
+    h.update(idx.cpu().numpy().astype(np.int32).tobytes())
+    return h.hexdigest()
+
+
 def golden_totals(name):
     import json
     import os
@@ -109,11 +117,12 @@ def golden_totals(name):
 
 
 def test_full_c2_totals_golden(arb, c2):
-    # k = 3, 4 totals of the whole graph against the oracle's (tests/golden/make_fullsize.py)
+    # k = 3, 4, 5 totals of the whole graph against the oracle's (tests/golden/make_fullsize.py)
     g, o, feat, host = c2
     ref = golden_totals("c2")
     assert (ref["n"], ref["m"]) == (g.n, g.m)
-    for k in (3, 4):
+    ref["totals"].update(golden_totals("c2k5")["totals"])
+    for k in (3, 4, 5):
         ws = arb.CountWorkspace(o["ooff"], o["oidx"], k)
         assert arb.arb_count(o["ooff"], o["oidx"], k, opts=bench_opts(arb, o, feat, k, ws), ws=ws) == \
             ref["totals"][str(k)]
@@ -245,12 +254,13 @@ def _orientation_properties(arb, o, n, eps=1.0):
 
 
 def test_full_c5a_rmat26_k4(arb, orc):
-    """R-MAT scale 26 (2^30 samples, 2^26 vertices, ~1.05 billion edges, built on the GPU):
-    orientation invariants at full size, k = 4 total = sum of per-root counts, per-root
+    """R-MAT scale 26 (2^30 samples, 2^26 vertices, ~1.05 billion edges, built on the GPU
+    from the counter-based stream): orientation invariants at full size, k = 4 total =
+    sum of per-root counts (the whole-graph oracle count is hours of host time), per-root
     counts of the heaviest roots (2926 out-neighbours: the big-root path) and of every
     tier against the oracle, per-vertex counts of sampled vertices."""
     say("generating R-MAT scale 26 on the GPU")
-    n, off, idx = gg.rmat_device(26, 1 << 30, seed=51)
+    n, off, idx = gg.rmat_cb_device(26, 1 << 30, seed=51)
     assert arb.arb_validate(off, idx) == 0
     o = arb.arb_orient(off, idx, eps=1.0)
     _orientation_properties(arb, o, n)
@@ -283,10 +293,15 @@ def test_full_c5a_rmat26_k4(arb, orc):
 
 def test_full_c5b_rgg3d(arb, orc):
     """3-D random geometric graph, 2^24 points on the unit torus, mean degree 40 (~335M
-    edges, built on the GPU): k = 5, 6, 7 with per-vertex counts; per-root and per-vertex
-    counts of sampled roots / vertices against the oracle; sums against the totals."""
+    edges, built on the GPU from the counter-based stream, byte-identical to the host's
+    build): k = 5, 6, 7 totals against the oracle's, with per-vertex counts; per-root
+    and per-vertex counts of sampled roots / vertices against the oracle; sums against
+    the totals."""
     say("generating the 3-D random geometric graph on the GPU")
-    n, off, idx = gg.rgg_device(1 << 24, 40.0, seed=52)
+    n, off, idx = gg.rgg_cb_device(1 << 24, 40.0, seed=52)
+    ref = golden_totals("c5b")
+    assert (n, idx.numel() // 2) == (ref["n"], ref["m"])
+    assert csr_digest(off, idx) == ref["sha256"]          # the graph the oracle counted
     assert arb.arb_validate(off, idx) == 0
     o = arb.arb_orient(off, idx, eps=1.0)
     _orientation_properties(arb, o, n)
@@ -302,6 +317,7 @@ def test_full_c5b_rgg3d(arb, orc):
         pr = arb.u64_numpy(per_root)
         del per_root
         assert int(pr.sum(dtype=np.uint64)) == t
+        assert t == ref["totals"][str(k)], k
         _sample_and_check_roots(arb, orc, n, o, pr, k, np.random.default_rng(60 + k), rand=500)
         tp, pv_rank = arb.arb_count(o["ooff"], o["oidx"], k, per_vertex=True, ws=ws)
         assert tp == t and int(pv_rank.sum(dtype=np.uint64)) == (k * t) % (1 << 64)

@@ -58,6 +58,11 @@ def test_features_per_root_and_work(arb, orc, gi):
         work = torch.empty(n, dtype=torch.int64, device="cuda")
         tot = arb.arb_count_async(o["ooff"], o["oidx"], k, per_root=per_root)
         arb.arb_count_async(o["ooff"], o["oidx"], k, work=work)
+        work2, cyc = arb.arb_count_instrumented(o["ooff"], o["oidx"], k, cycles=True)
+        torch.cuda.synchronize()
+        assert torch.equal(work2, work)
+        live = torch.from_numpy(np.diff(ref["ooff"]) >= k - 1).cuda()
+        assert bool((cyc[live] > 0).all()) and bool((cyc[~live] == 0).all())
         torch.cuda.synchronize()
         pr = arb.u64_numpy(per_root)
         assert np.array_equal(pr, lc[:, k - 2])                  # (k-1)-cliques of G[N+(v)]
