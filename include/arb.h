@@ -257,6 +257,22 @@ int arb_count_batch_async(const arb_ocsr *dg, const int64_t *graph_vtx_offsets, 
                           uint64_t *per_vertex, uint64_t *totals_dev, uint64_t *total_dev,
                           const arb_count_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): arb_count_async without a caller
+ * workspace.  Its scratch is a file-scope device array of ARB_NOALLOC_SCRATCH_BYTES that
+ * each GPU the library runs on holds until the process ends; the call makes no
+ * allocation of its own.  Graphs whose arb_count_workspace(n, m, k) exceeds that size are
+ * rejected with ARB_ELIMIT before any work is enqueued.  The tier kernels run on `stream`
+ * only (concurrent_tiers is ignored) and launch timing is not recorded.  Every call on a
+ * GPU shares that GPU's array and clears what must start at zero, so calls that overlap
+ * on one GPU (different streams or host threads) race: serialise them.  Arguments,
+ * outputs and other errors as arb_count_async with per_root = work_out = NULL.
+ */
+#define ARB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int arb_count_noalloc(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,
+                      const arb_count_opts *opts, void *stream);
+
 /* Synchronous arb_count_async that also checks dg first; returns the total, or 0 with
  * arb_last_error() != ARB_OK on failure.  Synchronises the stream. */
 uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex,

@@ -36,6 +36,7 @@ ARB_MAX_K = _define("ARB_MAX_K") or 10
 ARB_MAX_LOCAL = _define("ARB_MAX_LOCAL") or 768
 ARB_MAX_ROUNDS = _define("ARB_MAX_ROUNDS") or 64
 ARB_MLP_PARAMS = _define("ARB_MLP_PARAMS") or 8641
+ARB_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class ArbError(RuntimeError):
@@ -88,6 +89,7 @@ _sigs = {
     "arb_count_async": ([P, I32, P, P, P, P, P, P, SZ, P], I32),
     "arb_segment_sum_u64": ([P, P, I64, P, P], I32),
     "arb_count": ([P, I32, P, P, P, SZ, P], ctypes.c_uint64),
+    "arb_count_noalloc": ([P, I32, P, P, P, P], I32),
     "arb_count_instrumented": ([P, I32, P, P, P, P, SZ, P], I32),
     "arb_features": ([P, P, P, P, P], I32),
     "arb_mlp_forward": ([P, P, I64, P, P, P], I32),
@@ -435,6 +437,17 @@ def arb_count_instrumented(ooff, oidx, k, cycles=False, opts=None, ws=None, stre
                                        ctypes.byref(opts) if opts is not None else None, _ptr(ws.buf), ws.buf.numel(),
                                        _stream(stream)), "arb_count_instrumented")
     return work[:n], (cyc[:n] if cyc is not None else None)
+
+
+def arb_count_noalloc(ooff, oidx, k, total=None, per_vertex=None, opts=None, stream=None):
+    """Enqueue arb_count_noalloc (no workspace argument); returns the device total tensor."""
+    dg = _ocsr(ooff, oidx)
+    if total is None:
+        total = torch.empty(1, dtype=torch.int64, device=ooff.device)
+    rc = _lib.arb_count_noalloc(ctypes.byref(dg), int(k), _ptr(total), _ptr(per_vertex),
+                                ctypes.byref(opts) if opts is not None else None, _stream(stream))
+    _check(rc, "arb_count_noalloc")
+    return total
 
 
 def arb_count_batch_workspace(n: int, m: int, k: int, G: int) -> int:

@@ -2,6 +2,7 @@
 // (root sort by tier and cost, expansion into items) and the tier launches.
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "count_kernels.h"
@@ -280,7 +281,7 @@ struct Profile {
     std::vector<ProfTotal> totals;
 };
 static Profile g_prof;
-// set while launch-timing events must not be created
+// set while arb_count_noalloc runs: no launch-timing events are created
 static thread_local bool g_no_events = false;
 
 static int prof_event(hipEvent_t *e) {
@@ -669,6 +670,51 @@ extern "C" uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex, c
     }
     set_error(ARB_OK);
     return h;
+}
+
+// ------------------------------------------------------------------ allocation-free entry point
+//
+// arb_count_noalloc takes its workspace from this file-scope device array instead of a
+// caller buffer.  Each device holds its own copy for the life of the process; host code
+// reaches it only through the address hipGetSymbolAddress returns on that device (the
+// array's name in host code is not a device address).
+constexpr size_t kNoAllocScratch = ARB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+constexpr int kNoAllocDevices = 64;
+static void *g_scratch_ptr[kNoAllocDevices];
+static std::mutex g_scratch_mu;
+
+static int noalloc_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ARB_EHIP;
+    if (dev < 0 || dev >= kNoAllocDevices) return ARB_ELIMIT;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ARB_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ARB_OK;
+}
+
+extern "C" int arb_count_noalloc(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64_t *per_vertex,
+                                 const arb_count_opts *opts, void *stream) {
+    int rc = ARB_OK;
+    void *ws = nullptr;
+    if (!ocsr_ok(dg) || !total_dev || k < 1 || k > ARB_MAX_K) rc = ARB_EINVAL;
+    else if (arb_count_workspace(dg->n, dg->m, k) > kNoAllocScratch) rc = ARB_ELIMIT;
+    else rc = noalloc_scratch(&ws);
+    if (rc) { set_error(rc); return rc; }
+    arb_count_opts o;
+    arb_count_default_opts(&o);
+    if (opts) o = *opts;
+    o.concurrent_tiers = 0;          // the caller's stream only: no library streams or events
+    g_no_events = true;
+    rc = count_impl(dg, k, total_dev, per_vertex, nullptr, nullptr, &o, ws, kNoAllocScratch, as_stream(stream));
+    g_no_events = false;
+    set_error(rc);
+    return rc;
 }
 
 extern "C" int arb_profile_enable(int on) {
