@@ -57,7 +57,7 @@ def parse():
                     help="only the headline's timed steps (profiling runs): no other schedule, workload or study")
     ap.add_argument("--no-studies", action="store_true", help="skip the studies of the other rows")
     ap.add_argument("--no-rmat26", action="store_true", help="skip the R-MAT scale-26 workload")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="expected CPU-baseline time (sets its limit)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (counter calibration)")
     return ap.parse_args()
@@ -122,84 +122,72 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_child(path, k, budget, threads):
-    """Child process: the CPU oracle (Chiba-Nishizeki, OpenMP over roots) on every
-    stride-th root of its degree order, the stride shrinking until a run takes about
-    `budget` seconds; also the oracle's setup alone (a stride of n: one root).  Prints one
-    JSON line per run."""
+def cpu_child(path, ks, threads):
+    """Child process: the CPU oracle (Chiba-Nishizeki, OpenMP over roots) on the whole
+    sample graph for each k on `threads` host threads, then k = 3 on one thread (the
+    oracle's authority build).  Prints one JSON line per run."""
     import numpy as np
     import oracle
     from paper_2002_10047_amd import graphgen as gg
     z = np.load(path)
     g = gg.Graph(int(z["n"]), z["offsets"], z["indices"])
-    t1 = time.time()
-    oracle.count(g, k, nthreads=threads, stride=g.n, phase=0)
-    setup = time.time() - t1
-    stride = 1 << 14
-    while True:
+    for k, th in [(k, threads) for k in ks] + [(3, 1)]:
         t1 = time.time()
-        c = oracle.count(g, k, nthreads=threads, stride=stride, phase=stride // 2)
-        dt = time.time() - t1
-        print(json.dumps({"k": k, "stride": stride, "count": c, "seconds": dt, "setup": setup,
-                          "threads": threads}), flush=True)
-        if dt - setup >= budget / 3 or stride == 1:
-            break
-        stride = max(1, stride // 4)
+        c = oracle.count(g, k, nthreads=th)
+        print(json.dumps({"k": k, "threads": th, "count": c, "seconds": time.time() - t1}), flush=True)
 
 
-def cpu_run(path, k, budget, threads):
+def cpu_baseline(ks, seconds, exact, n_full):
+    """The CPU oracle on a bounded sample of the headline workload: the whole 3-D torus RGG
+    of the same recipe (mean degree 40, the counter-based stream, seed 52) with 2^19
+    vertices, 1/32 of the headline's.  Its cliques per vertex match the full graph's (the
+    recipe is scale-free at fixed mean degree; the counts times 32 are compared with the
+    oracle's full-graph totals), so cliques/s on it stand for the oracle's rate on the
+    full graph.  CPU_THREADS threads (the host-core share of one GPU), plus k = 3 on one
+    thread."""
     import subprocess
-    try:
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", path, str(k), str(budget),
-                            str(threads)], capture_output=True, text=True, timeout=max(60.0, 8 * budget))
-        lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
-    except subprocess.TimeoutExpired as e:
-        lines = [l for l in (e.stdout or b"").decode().splitlines() if l.startswith("{")]
-    return json.loads(lines[-1]) if lines else None
-
-
-def cpu_baseline(n, off_h, idx_h, ks, seconds, exact):
-    """The CPU oracle on the headline graph: per k, a strided root sample of its degree
-    order on CPU_THREADS host threads, projected to the whole graph (count x stride; time
-    = setup + (run - setup) x stride); the projected count is compared with the oracle's
-    stored whole-graph total.  Plus one single-thread run (the oracle's authority build)
-    at k = 3."""
     import tempfile
     import numpy as np
-    budget = seconds / (len(ks) + 1)
+    from paper_2002_10047_amd import graphgen as gg
+    ns = 1 << 20
+    n, off, idx = gg.rgg_cb_device(ns, 40.0, seed=52)
+    off_h, idx_h = off.cpu().numpy(), idx.cpu().numpy()
+    del off, idx
     out = {"unit": "k-cliques/s", "cores": CPU_THREADS, "kind": "oracle", "nproc": os.cpu_count(),
            "cpu_model": cpu_model(), "per_k": {}}
+    lines = []
     with tempfile.TemporaryDirectory() as td:
         path = os.path.join(td, "g.npz")
-        np.savez(path, n=n, offsets=off_h, indices=idx_h)
-        cnt_x = t_x = 0.0
-        for k in ks:
-            r = cpu_run(path, k, budget, CPU_THREADS)
-            if not r or r["seconds"] <= 0:
-                continue
-            proj_t = r["setup"] + max(r["seconds"] - r["setup"], 0.0) * r["stride"]
-            proj_c = r["count"] * r["stride"]
-            e = {"stride": r["stride"], "sample_count": r["count"], "seconds": r["seconds"], "setup_s": r["setup"],
-                 "projected_count": proj_c, "projected_s": proj_t, "cliques_per_s": proj_c / proj_t}
-            if exact and str(k) in exact:
-                e["projected_over_exact"] = proj_c / exact[str(k)]
-            out["per_k"][str(k)] = e
-            cnt_x += proj_c
-            t_x += proj_t
-            log(f"cpu oracle k={k}: {e}")
-        r = cpu_run(path, 3, budget, 1)
-        if r:
-            proj_t = r["setup"] + max(r["seconds"] - r["setup"], 0.0) * r["stride"]
-            out["single_thread_k3"] = {"stride": r["stride"], "sample_count": r["count"], "seconds": r["seconds"],
-                                       "projected_count": r["count"] * r["stride"], "projected_s": proj_t,
-                                       "cliques_per_s": r["count"] * r["stride"] / proj_t}
-    if t_x <= 0:
+        np.savez(path, n=ns, offsets=off_h, indices=idx_h)
+        try:
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", path,
+                                ",".join(str(k) for k in ks), str(CPU_THREADS)], capture_output=True, text=True,
+                               timeout=max(60.0, 6 * seconds))
+            lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+        except subprocess.TimeoutExpired as e:
+            lines = [l for l in (e.stdout or b"").decode().splitlines() if l.startswith("{")]
+    cnt = tsum = 0.0
+    for l in lines:
+        e = json.loads(l)
+        if e["threads"] == 1:
+            out["single_thread_k3"] = {"count": e["count"], "seconds": e["seconds"],
+                                       "cliques_per_s": e["count"] / e["seconds"]}
+            continue
+        k = e["k"]
+        pk = {"count": e["count"], "seconds": e["seconds"], "cliques_per_s": e["count"] / e["seconds"]}
+        if exact and str(k) in exact:
+            pk["count_x_scale_over_exact"] = e["count"] * (n_full / ns) / exact[str(k)]
+        out["per_k"][str(k)] = pk
+        cnt += e["count"]
+        tsum += e["seconds"]
+        log(f"cpu oracle k={k}: {pk}")
+    if tsum <= 0:
         return None
-    out["value"] = cnt_x / t_x
-    out["sample"] = (f"Chiba-Nishizeki oracle (OpenMP over roots, {CPU_THREADS} threads) on the headline graph; per k "
-                     "the roots at positions p % stride == stride/2 of its degree order, projected to all roots "
-                     "(count x stride, setup + (time - setup) x stride); value = sum of projected counts / sum of "
-                     "projected times over k; projected_over_exact compares with the oracle's whole-graph total")
+    out["value"] = cnt / tsum
+    out["sample"] = (f"the whole 3-D torus RGG of the headline's recipe with 2^20 vertices (mean degree 40, seed 52; "
+                     f"1/{n_full // ns} of the headline graph), k = {ks}, Chiba-Nishizeki oracle on {CPU_THREADS} "
+                     "threads; value = sum of counts / sum of seconds; count_x_scale_over_exact compares its counts "
+                     "times the size ratio with the oracle's totals of the full graph")
     return out
 
 
@@ -350,7 +338,7 @@ def roofline(arb, np, torch, o, ks, pv, opts_of_k, prof, workload):
 class Workload:
     """A resident graph, its orientation, workspaces and per-schedule options for ks."""
 
-    def __init__(self, arb, torch, name, n, off, idx, ks, eps, pv, a, log_prefix):
+    def __init__(self, arb, torch, name, n, off, idx, ks, eps, pv, a, log_prefix, tune=True):
         from paper_2002_10047_amd import learn, tuning
         self.arb, self.torch, self.name, self.n, self.off, self.idx, self.ks, self.eps, self.pv = \
             arb, torch, name, n, off, idx, ks, eps, pv
@@ -372,7 +360,7 @@ class Workload:
             for k in ks:
                 w = self.weights[k] if sname == "learned" else None
                 f = self.feat if sname == "learned" else None
-                if a.no_tune:
+                if a.no_tune or not tune:
                     op = arb.count_opts(schedule=tuning.SCHEDULES[sname], mlp_weights=w, features=f)
                 else:
                     op, _ = tuning.tuned_opts(self.o["ooff"], self.o["oidx"], k, sname, mlp_weights=w, features=f,
@@ -448,7 +436,7 @@ class Workload:
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--cpu-child":
-        cpu_child(sys.argv[2], int(sys.argv[3]), float(sys.argv[4]), int(sys.argv[5]))
+        cpu_child(sys.argv[2], [int(x) for x in sys.argv[3].split(",")], int(sys.argv[4]))
         return
     a = parse()
     if a.gpus != 1:
@@ -505,9 +493,6 @@ def main():
         t = t_k[k]
         out["per_k"][str(k)].update({"alu_Tops": u["alu"] / t / 1e12, "alu_frac": u["alu"] / t / 1e12 / PEAK_ALU_TOPS,
                                      "lds_GBs": u["lds"] / t / 1e9, "hbm_GBs": u["hbm"] / t / 1e9})
-    off_h = idx_h = None
-    if not a.no_cpu_baseline:
-        off_h, idx_h = off.cpu().numpy(), idx.cpu().numpy()
     del hw, off, idx
     torch.cuda.empty_cache()
 
@@ -517,7 +502,8 @@ def main():
         n26, off26, idx26 = gg.rmat_cb_device(26, 1 << 30, seed=51)
         torch.cuda.synchronize()
         log(f"R-MAT 26: n={n26} m={idx26.numel() // 2} generated on the GPU in {time.time() - t0:.1f}s")
-        w26 = Workload(arb, torch, "rmat26", n26, off26, idx26, [4], a.eps, False, a, "rmat26")
+        # library defaults: a search on this graph takes several seconds per candidate
+        w26 = Workload(arb, torch, "rmat26", n26, off26, idx26, [4], a.eps, False, a, "rmat26", tune=False)
         ms26, tot26 = w26.timed(main_name, 2, 1)
         sch = w26.compare_schedules(main_name, ms26, tot26, 2, 1)
         t_or, t_k = w26.phases(main_name)
@@ -550,7 +536,7 @@ def main():
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, off_h, idx_h, ks, a.cpu_seconds, exact)
+        out["cpu_baseline"] = cpu_baseline(ks, a.cpu_seconds, exact, n)
     copy_calibration(a, torch)
     print(json.dumps(out), flush=True)
 

@@ -7,14 +7,14 @@
 //   * S and an LDS hash from id to local id serve the second level; the gathered N+(u)
 //     lists set row bits with global atomics (upper rows: row x = x's neighbours above x;
 //     symmetric rows in the per-vertex mode);
-//   * the pair phase is wave-cooperative: a wave claims a row x and holds it across its
-//     lanes (lane l: words l and l + 64, rows of up to 4096 bits), then for each member y
-//     of the row it reads row y with one coalesced load per lane and forms
-//     J = row x AND row y above y;
-//   * k - 1 = 3 (k = 4 roots, k = 5 pairs): each lane adds the popcount of its words of
-//     J; deeper: a walk over J in which every set is held across the lanes the same way
-//     (members taken in ascending order with a ballot; frames of a private stack for the
-//     levels above the last), each node costing one coalesced row read.
+//   * k - 1 = 3 (k = 4 roots, k = 5 pairs): the pairs (x, y) go through per-wave rings
+//     to the lanes, each adding popcount(row x AND row y) over the words from y's on;
+//   * deeper: the pair phase is wave-cooperative: a wave claims a row x and holds it
+//     across its lanes (lane l: words l and l + 64, rows of up to 4096 bits), then for each
+//     member y of the row it reads row y with one coalesced load per lane and walks
+//     J = row x AND row y above y, every set held across the lanes the same way (members
+//     taken in ascending order with a ballot; frames of a private stack for the levels
+//     above the last two), each node costing one coalesced row read.
 // Per-vertex counts as in the tiers: at a node needing two more vertices with set I, each
 // z in I gains popcount(I AND adj(z)), the chosen vertices gain the node's cliques.
 #include "count_kernels.h"
@@ -30,10 +30,14 @@ struct BigLds {
     static constexpr int HS = 2 * kBigMax;
     static constexpr int HB = 13;
     static constexpr int SPAN = 0;          // membership always through the hash
+    static constexpr int RING = 128;        // per-wave pair ring, rows written in windows
     int32_t S[kBigMax];
     unsigned long long H[HS];
     unsigned long long cnt[PV ? kBigMax : 1];
-    ListEnt lt[TW][64];
+    union {
+        uint32_t ring[TW][RING];    // pair phase at k - 1 = 3: (x << 16 | y) per pair
+        ListEnt lt[TW][64];         // second level
+    } q;
     unsigned long long red[TW];
     int d;
     int pop;
@@ -46,7 +50,7 @@ static_assert(sizeof(BigLds<true>) <= 160 * 1024, "big-item LDS");
 template <bool PV, bool SYM, class Lds>
 __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int32_t first, int32_t last, int wv,
                            int lane, uint32_t *grow, int W, unsigned long long &mine, unsigned long long &words) {
-    AS3<ListEnt> *lt = T->lt[wv];
+    AS3<ListEnt> *lt = T->q.lt[wv];
     const int nl = wv < d ? (d - wv + Lds::TW - 1) / Lds::TW : 0;
     for (int gb = 0; gb < nl; gb += 64) {
         const int t = gb + lane;
@@ -113,6 +117,33 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int
         }
         wave_fence();
     }
+}
+
+// One pair (x, y), x < y, at k - 1 = 3: popcount(row x AND row y) over the members above y
+// (the words at or above y's word; rows may be symmetric); per-vertex: each common member
+// z above y gains 1, x and y gain the pair's count
+template <bool PV, class Lds>
+__device__ __forceinline__ unsigned big_pair(AS3<Lds> *T, const uint32_t *grow, int W, int x, int y) {
+    const uint32_t *rx = grow + (int64_t)x * W;
+    const uint32_t *ry = grow + (int64_t)y * W;
+    unsigned c = 0;
+    for (int w = y >> 5; w < W; ++w) {
+        uint32_t t = rx[w] & ry[w] & gtmask(y, w);
+        c += __popc(t);
+        if constexpr (PV) {
+            while (t) {
+                lds_add(&T->cnt[w * 32 + __ffs(t) - 1], 1ull);
+                t &= t - 1;
+            }
+        }
+    }
+    if constexpr (PV) {
+        if (c) {
+            lds_add(&T->cnt[x], (unsigned long long)c);
+            lds_add(&T->cnt[y], (unsigned long long)c);
+        }
+    }
+    return c;
 }
 
 // A set of local ids held across the wave: lane l keeps words l (h0) and l + 64 (h1).
@@ -343,48 +374,86 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
             __syncthreads();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int pneed = need - 2;
-            int x = wv;
-            while (x < d) {
-                WSet rx = wload(grow + (int64_t)x * W, W, lane);
-                if constexpr (PV) rx = wabove(rx, x, lane);       // symmetric rows: members above x
-                WSet Y = rx;
-                unsigned long long cx = 0;                         // per-vertex: cliques through x
-                while (true) {
-                    const int y = wpop(Y, lane);
-                    if (y < 0) break;
-                    if constexpr (INSTR) nodes += lane == 0 ? 1ull : 0ull;
-                    WSet ry = wload(grow + (int64_t)y * W, W, lane);
-                    const WSet J = PV ? wabove(wand(rx, ry), y, lane) : wand(rx, ry);
-                    unsigned long long c;
-                    if (pneed == 1) {
-                        c = wpopc(J);
-                        if constexpr (PV) {
-                            uint32_t t0 = J.h0, t1 = J.h1;
-                            while (t0) {
-                                lds_add(&T->cnt[lane * 32 + __ffs(t0) - 1], 1ull);
-                                t0 &= t0 - 1;
-                            }
-                            while (t1) {
-                                lds_add(&T->cnt[(lane + 64) * 32 + __ffs(t1) - 1], 1ull);
-                                t1 &= t1 - 1;
-                            }
+            if (pneed == 1) {
+                // k - 1 = 3: pairs through per-wave rings to the lanes, a lane per pair (the
+                // lanes' rows are read from L2, word by word from y's word on)
+                AS3<uint32_t> *ring = T->q.ring[wv];
+                unsigned head = 0, tail = 0;
+                int x = wv;
+                while (x < d) {
+                    const uint32_t *rx = grow + (int64_t)x * W;
+                    for (int cw = 0; cw < W; cw += 64) {
+                        uint32_t bits = cw + lane < W ? rx[cw + lane] : 0u;
+                        if constexpr (PV) bits &= gtmask(x, cw + lane);      // symmetric rows
+                        const unsigned c = __popc(bits);
+                        unsigned pre = c;
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const unsigned y = __shfl_up(pre, o, 64);
+                            if (lane >= o) pre += y;
                         }
-                    } else {
-                        c = wdfs<PV, INSTR, Lds>(T, grow, W, J, pneed, lane, &nodes);
+                        const unsigned stop_all = tail + __shfl(pre, 63, 64);
+                        unsigned pos = tail + pre - c;
+                        while (true) {
+                            while (bits && pos - head < (unsigned)Lds::RING) {
+                                const int bb = __ffs(bits) - 1;
+                                bits &= bits - 1;
+                                ring[pos & (Lds::RING - 1)] = ((uint32_t)x << 16) | (uint32_t)((cw + lane) * 32 + bb);
+                                ++pos;
+                            }
+                            wave_fence();
+                            const bool all = stop_all - head <= (unsigned)Lds::RING;
+                            const unsigned stop = all ? stop_all : head + Lds::RING;
+                            while (stop - head >= 64) {
+                                const uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
+                                mine += big_pair<PV, Lds>(T, grow, W, (int)(p >> 16), (int)(p & 0xffffu));
+                                if constexpr (INSTR) nodes += 1;
+                                head += 64;
+                            }
+                            wave_fence();
+                            if (all) break;
+                        }
+                        tail = stop_all;
                     }
-                    mine += c;
+                    int nx = 0;
+                    if (lane == 0) nx = __hip_atomic_fetch_add(&T->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    x = __shfl(nx, 0, 64);
+                }
+                if (tail != head && lane < (int)(tail - head)) {
+                    const uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
+                    mine += big_pair<PV, Lds>(T, grow, W, (int)(p >> 16), (int)(p & 0xffffu));
+                    if constexpr (INSTR) nodes += 1;
+                }
+            } else {
+                // deeper: a wave per row x, J = row x AND row y held across the lanes, walked
+                // by the wave
+                int x = wv;
+                while (x < d) {
+                    WSet rx = wload(grow + (int64_t)x * W, W, lane);
+                    if constexpr (PV) rx = wabove(rx, x, lane);       // symmetric rows: members above x
+                    WSet Y = rx;
+                    unsigned long long cx = 0;                         // per-vertex: cliques through x
+                    while (true) {
+                        const int y = wpop(Y, lane);
+                        if (y < 0) break;
+                        if constexpr (INSTR) nodes += lane == 0 ? 1ull : 0ull;
+                        WSet ry = wload(grow + (int64_t)y * W, W, lane);
+                        const WSet J = PV ? wabove(wand(rx, ry), y, lane) : wand(rx, ry);
+                        const unsigned long long c = wdfs<PV, INSTR, Lds>(T, grow, W, J, pneed, lane, &nodes);
+                        mine += c;
+                        if constexpr (PV) {
+                            const unsigned long long t = wave_sum(c);
+                            if (lane == 0 && t) lds_add(&T->cnt[y], t);
+                            cx += t;
+                        }
+                    }
                     if constexpr (PV) {
-                        const unsigned long long t = wave_sum(c);
-                        if (lane == 0 && t) lds_add(&T->cnt[y], t);
-                        cx += t;
+                        if (lane == 0 && cx) lds_add(&T->cnt[x], cx);
                     }
+                    int nx = 0;
+                    if (lane == 0) nx = __hip_atomic_fetch_add(&T->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    x = __shfl(nx, 0, 64);
                 }
-                if constexpr (PV) {
-                    if (lane == 0 && cx) lds_add(&T->cnt[x], cx);
-                }
-                int nx = 0;
-                if (lane == 0) nx = __hip_atomic_fetch_add(&T->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                x = __shfl(nx, 0, 64);
             }
         }
         const unsigned long long item = team_sum<TW, 1>(T, mine, wv, lane);

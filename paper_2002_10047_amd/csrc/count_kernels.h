@@ -171,6 +171,25 @@ __device__ __forceinline__ void load_row(const AS3<Lds> *T, int z, uint32_t (&r)
     }
 }
 
+// r[w] &= word w of bit row z, for every w < W, as Q-word LDS loads
+template <int W, class Lds>
+__device__ __forceinline__ void and_row(const AS3<Lds> *T, int z, uint32_t (&r)[W]) {
+    constexpr int Q = Lds::Q;
+    const AS3<uint32_t> *p = &T->rows[z * Lds::RS];
+#pragma unroll
+    for (int q = 0; q < W / Q; ++q) {
+        if constexpr (Q == 4) {
+            const u32x4 v = *reinterpret_cast<const AS3<u32x4> *>(p + 4 * q);
+            r[4 * q] &= v.x;
+            r[4 * q + 1] &= v.y;
+            r[4 * q + 2] &= v.z;
+            r[4 * q + 3] &= v.w;
+        } else {
+            r[q] &= p[q];
+        }
+    }
+}
+
 constexpr uint64_t kEmpty = ~0ull;
 
 __device__ __forceinline__ uint32_t hslot(uint32_t key, int hb) {
@@ -339,8 +358,69 @@ __device__ __forceinline__ Acc dfs(AS3<Lds> *T, Bits<W> J) {
     return dfs_body<W, PV, INSTR, L, Lds>(T, J);
 }
 
+// The 64-tier (W = 2: local ids < 64) walks its sets as 64-bit words: one find-first-set
+// per member, one 8-byte row read, and the leaf takes two members per step so that their
+// row reads are in flight together.
+template <class Lds>
+__device__ __forceinline__ uint64_t row64(const AS3<Lds> *T, int z) {
+    const AS3<uint32_t> *p = &T->rows[z * Lds::RS];
+    return (uint64_t)p[0] | ((uint64_t)p[1] << 32);
+}
+
+template <bool PV, bool INSTR, int L, class Lds>
+__device__ __forceinline__ Acc dfs64(AS3<Lds> *T, uint64_t J);
+
+template <bool PV, bool INSTR, int L, class Lds>
+__device__ __attribute__((noinline)) Acc dfs64_body(AS3<Lds> *T, uint64_t J) {
+    return dfs64<PV, INSTR, L, Lds>(T, J);
+}
+
+template <bool PV, bool INSTR, int L, class Lds>
+__device__ __forceinline__ Acc dfs64(AS3<Lds> *T, uint64_t J) {
+    Acc out{0ull, 0ull};
+    if constexpr (INSTR) out.nodes += (unsigned long long)__popcll(J);
+    uint64_t R = J;                         // members not taken yet: those above the last one
+    if constexpr (L == 2) {
+        unsigned leaf = 0;
+        while (R) {
+            const int z1 = __builtin_ctzll(R);
+            R &= R - 1;
+            const uint64_t above1 = R;
+            const bool two = R != 0;
+            const int z2 = two ? __builtin_ctzll(R) : z1;
+            R &= R - 1;
+            const uint64_t r1 = row64(T, z1), r2 = row64(T, z2);
+            leaf += (unsigned)__popcll(above1 & r1) + (unsigned)__popcll(R & r2);   // R = 0 unless two
+            if constexpr (PV) {
+                // each member belongs to as many of the node's cliques as it has neighbours in J
+                const unsigned a1 = (unsigned)__popcll(J & r1);
+                if (a1) lds_add(&T->cnt[z1], (unsigned long long)a1);
+                const unsigned a2 = two ? (unsigned)__popcll(J & r2) : 0u;
+                if (a2) lds_add(&T->cnt[z2], (unsigned long long)a2);
+            }
+        }
+        out.c += leaf;
+    } else {
+        while (R) {
+            const int z = __builtin_ctzll(R);
+            R &= R - 1;
+            const uint64_t K = R & row64(T, z);
+            Acc sub;
+            if constexpr (L - 1 <= 3) sub = dfs64<PV, INSTR, L - 1, Lds>(T, K);
+            else sub = dfs64_body<PV, INSTR, L - 1, Lds>(T, K);
+            if constexpr (PV) {
+                if (sub.c) lds_add(&T->cnt[z], sub.c);
+            }
+            out.c += sub.c;
+            out.nodes += sub.nodes;
+        }
+    }
+    return out;
+}
+
 template <int W, bool PV, bool INSTR, int L, class Lds>
 __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, const Bits<W> &J) {
+    if constexpr (W == 2) return dfs64<PV, INSTR, L, Lds>(T, (uint64_t)J.w[0] | ((uint64_t)J.w[1] << 32));
     Acc out{0ull, 0ull};
     if constexpr (INSTR) {
         unsigned c = 0;
@@ -524,12 +604,33 @@ static_assert(ARB_MAX_K - 3 - kDeepMin + 4 <= kDeepFrames, "dfs_deep's frames co
 // extend it with `need` more vertices from S (need >= 1); .nodes as in dfs.
 template <int W, int LMAX, bool PV, bool INSTR, class Lds>
 __device__ __forceinline__ Acc do_pair(AS3<Lds> *T, int x, int y, int need) {
+    constexpr bool SYM = sym_rows<PV, LMAX>();
+    Acc out{0ull, INSTR ? 1ull : 0ull};
+    if (LMAX >= 2 && need >= 2) {
+        // J = row x AND row y (above y), ANDed in place one Q-word vector at a time so
+        // that the two rows are never held in registers together
+        Bits<W> J;
+        load_row<W, 0, Lds>(T, x, J.w);
+        and_row<W, Lds>(T, y, J.w);
+        if constexpr (SYM) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) J.w[w] &= gtmask(y, w);
+        }
+        const Acc sub = dfs_dispatch<W, LMAX, PV, INSTR, Lds>(T, J, need);
+        if constexpr (PV) {
+            if (sub.c) {
+                lds_add(&T->cnt[x], sub.c);
+                lds_add(&T->cnt[y], sub.c);
+            }
+        }
+        out.c = sub.c;
+        out.nodes += sub.nodes;
+        return out;
+    }
     uint32_t rx[W], ry[W];
     load_row<W, 0, Lds>(T, x, rx);
     load_row<W, 0, Lds>(T, y, ry);
-    constexpr bool SYM = sym_rows<PV, LMAX>();
-    Acc out{0ull, INSTR ? 1ull : 0ull};
-    if (need == 1 || LMAX < 2) {
+    {
         if constexpr (PV) {
             unsigned a = 0, c = 0;
 #pragma unroll
@@ -549,19 +650,6 @@ __device__ __forceinline__ Acc do_pair(AS3<Lds> *T, int x, int y, int need) {
         }
         return out;
     }
-    Bits<W> J;
-#pragma unroll
-    for (int w = 0; w < W; ++w) J.w[w] = rx[w] & ry[w] & (SYM ? gtmask(y, w) : ~0u);
-    const Acc sub = dfs_dispatch<W, LMAX, PV, INSTR, Lds>(T, J, need);
-    if constexpr (PV) {
-        if (sub.c) {
-            lds_add(&T->cnt[x], sub.c);
-            lds_add(&T->cnt[y], sub.c);
-        }
-    }
-    out.c = sub.c;
-    out.nodes += sub.nodes;
-    return out;
 }
 
 // ------------------------------------------------------------------ second level
@@ -909,10 +997,11 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
 }
 
 // Waves per SIMD the register allocation must allow: in the two smallest tiers the
-// latency of the list reads dominates, and more resident waves hide more of it (measured:
-// 5 beats the 3-4 that their register use would give, at every depth; 6 is slower)
+// latency of the list reads and of the LDS row reads of the walk dominates, and more
+// resident waves hide more of it (measured: 5 beats the 3-4 that their register use would
+// give, at every depth, for totals and per-vertex counts alike; 6 is slower)
 template <int W, bool PV, int LMAX> constexpr int tier_min_waves() {
-    return PV ? 1 : (W == 2 || W == 4 ? 5 : 1);
+    return W == 2 || W == 4 ? 5 : 1;
 }
 
 template <int W, int LMAX, bool PV, bool INSTR>
