@@ -57,6 +57,8 @@ def parse():
                     help="only the headline's timed steps (profiling runs): no other schedule, workload or study")
     ap.add_argument("--no-studies", action="store_true", help="skip the studies of the other rows")
     ap.add_argument("--no-rmat26", action="store_true", help="skip the R-MAT scale-26 workload")
+    ap.add_argument("--only", default="", choices=["", "rmat26", "rmat20"],
+                    help="profiling runs: only this workload's timed steps with the chosen schedule (no JSON line)")
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="expected CPU-baseline time (sets its limit)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (counter calibration)")
@@ -90,12 +92,15 @@ def algorithmic_units(arb, o, ks, np):
     """Per-root algorithmic units from the instrumented count: gather words and the
     numbers of search-tree nodes (c_j(v), j-cliques inside G[N+(v)], summed over j <= k-2)."""
     import torch
-    ooff = o["ooff"].cpu().numpy()
-    oidx = o["oidx"].cpu().numpy()
-    n = len(ooff) - 1
-    d = np.diff(ooff)
-    gather = np.zeros(n, np.int64)
-    np.add.at(gather, np.repeat(np.arange(n), d), d[oidx])
+    ooff_t = o["ooff"]
+    dt = ooff_t[1:] - ooff_t[:-1]
+    # gather words of root v: sum of d+(u) over u in N+(v), as a segmented sum on the GPU
+    cs = torch.zeros(o["oidx"].numel() + 1, dtype=torch.int64, device=ooff_t.device)
+    torch.cumsum(dt[o["oidx"].long()], 0, out=cs[1:])
+    gather = (cs[ooff_t[1:]] - cs[ooff_t[:-1]]).cpu().numpy()
+    del cs
+    d = dt.cpu().numpy()
+    n = len(d)
     W = (d + 31) // 32
     nodes = {}
     for k in sorted(set(ks) | {k - 1 for k in ks if k >= 4} | {3}):
@@ -244,17 +249,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary,
-    if it was taken on the current kernel sources; else None."""
+def measured_counters(kernel, workload):
+    """The committed rocprofv3 counter summary of `kernel` on `workload` (HBM bytes per
+    launch, VALU and LDS instruction counts), if it was taken on the current kernel
+    sources; else None."""
     p = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         t = json.load(f)
-    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
+    w = t.get("workloads", {}).get(workload)
+    if w is None or w.get("source_hash") != kernel_source_hash():
         return None
-    e = t.get("kernels", {}).get(kernel)
+    return w.get("kernels", {}).get(kernel)
+
+
+def measured_traffic(kernel, workload):
+    e = measured_counters(kernel, workload)
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
@@ -325,8 +336,11 @@ def roofline(arb, np, torch, o, ks, pv, opts_of_k, prof, workload):
         sec = v["ms"] / 1e3 / v["launches"]
         unit, scale, peak = {"hbm": ("GB/s", 1e9, PEAK_HBM_GBS), "alu": ("Tops/s", 1e12, PEAK_ALU_TOPS),
                              "lds": ("GB/s", 1e9, peak_lds)}[bound]
+        mc = measured_counters(sym, workload)
         out = {"bound": bound, "achieved": per / sec / scale, "peak": peak, "unit": unit, "frac": fr[bound],
                "traffic": measured_traffic(sym, workload), "kernel": sym, "launches": v["launches"],
+               "measured": None if mc is None else {k: mc.get(k) for k in ("valu_issue_frac", "valu_insts",
+                                                                           "lds_insts", "avg_ms")},
                "launch_ms": v["ms"] / v["launches"], "algorithmic_per_launch": per, "fracs": fr,
                "rule": "the counting kernel with the largest total time over the timed steps",
                "peaks_measured": peaks, "kernels": kernels}
@@ -449,6 +463,20 @@ def main():
     from paper_2002_10047_amd import arb
     from paper_2002_10047_amd import graphgen as gg
 
+    if a.only == "rmat26":
+        n26, off26, idx26 = gg.rmat_cb_device(26, 1 << 30, seed=51)
+        w26 = Workload(arb, torch, "rmat26", n26, off26, idx26, [4], a.eps, False, a, "rmat26", tune=False)
+        w26.timed(a.schedule, a.steps, a.warmup)
+        copy_calibration(a, torch)
+        return
+    if a.only == "rmat20":
+        g = gg.config_graph("c2")
+        off20, idx20 = arb.to_device_csr(g)
+        w20 = Workload(arb, torch, "rmat20", g.n, off20, idx20, [3, 4, 5], a.eps, False, a, "rmat20")
+        w20.timed(a.schedule, a.steps, a.warmup)
+        copy_calibration(a, torch)
+        return
+
     # ---------------------------------------------------------------- headline: 3-D RGG
     ks = [5, 6, 7]
     t0 = time.time()
@@ -504,15 +532,19 @@ def main():
         log(f"R-MAT 26: n={n26} m={idx26.numel() // 2} generated on the GPU in {time.time() - t0:.1f}s")
         # library defaults: a search on this graph takes several seconds per candidate
         w26 = Workload(arb, torch, "rmat26", n26, off26, idx26, [4], a.eps, False, a, "rmat26", tune=False)
+        arb.arb_profile_enable(True)
         ms26, tot26 = w26.timed(main_name, 2, 1)
+        prof26 = [e for e in arb.arb_profile_read() if not e["instrumented"]]
+        arb.arb_profile_enable(False)
         sch = w26.compare_schedules(main_name, ms26, tot26, 2, 1)
         t_or, t_k = w26.phases(main_name)
+        rf26, _ = roofline(arb, np, torch, w26.o, [4], False, w26.opts[main_name], prof26, "rmat26_k4")
         out["rmat26_k4"] = {"n": n26, "m": w26.m, "total": tot26[4], "orient_s": t_or,
                             "oriented_edges_per_s": w26.m / t_or, "count_s": t_k[4],
                             "cliques_per_s": tot26[4] / t_k[4], "step_ms": sch["ms_per_step"],
                             "learned_gain_vs_degree": sch["learned_gain_vs_degree"],
                             "learned_gain_vs_plain": sch["learned_gain_vs_plain"],
-                            "opts": arb.opts_dict(w26.opts[main_name][4])}
+                            "opts": arb.opts_dict(w26.opts[main_name][4]), "roofline": rf26}
         log(f"rmat26 k=4: {out['rmat26_k4']}")
         del w26, off26, idx26
         torch.cuda.empty_cache()
