@@ -270,7 +270,9 @@ def measured_traffic(kernel, workload):
 
 
 def kernel_symbol(tier, k, pv):
-    if tier >= len(TIER_W):
+    if tier > len(TIER_W):
+        return f"k_count_big<{int(pv)},0> (overflowed pair items)"
+    if tier == len(TIER_W):
         return f"k_count_big<{int(pv)},0>"
     return f"k_count<{TIER_W[tier]},{max(1, min(k - 3, 8))},{int(pv)},0>"
 

@@ -281,7 +281,9 @@ uint64_t arb_count(const arb_ocsr *dg, int k, uint64_t *per_vertex,
 /* Launch timing of the counting kernels.  While enabled, each tier-kernel launch of
  * arb_count / arb_count_async / arb_autotune is bracketed by two HIP events on the
  * stream it runs on (tier t holds items whose candidate set fits 64, 128, 256, 384,
- * 512, 768 local vertices).  arb_profile_enable(1) clears the totals.  arb_profile_read
+ * 512, 768 local vertices; tier ARB_NUM_TIERS is the global-scratch kernel's launch for
+ * the larger roots, tier ARB_NUM_TIERS + 1 its launch for the pair items the tier
+ * kernels overflowed, when it runs apart).  arb_profile_enable(1) clears the totals.  arb_profile_read
  * waits for pending events and fills, for each (tier, k, per-vertex, instrumented)
  * seen, the number of launches and their summed duration in ms (host arrays of
  * max_entries); it returns the number of entries (which may exceed max_entries), or

@@ -314,14 +314,14 @@ static int prof_fold() {
 // events from the caller's stream; default priority).  One set per host thread.
 struct TierStreams {
     bool ready = false;
-    hipStream_t st[kNumTiers];
-    hipEvent_t fork, join[kNumTiers];
+    hipStream_t st[kNumTiers + 1];          // the tiers, then the global-scratch kernel
+    hipEvent_t fork, join[kNumTiers + 1];
 };
 static thread_local TierStreams g_ts;
 
 static int tier_streams_init() {
     if (g_ts.ready) return ARB_OK;
-    for (int t = 0; t < kNumTiers; ++t) {
+    for (int t = 0; t <= kNumTiers; ++t) {
         ARB_HIP(hipStreamCreateWithFlags(&g_ts.st[t], hipStreamNonBlocking));
         ARB_HIP(hipEventCreateWithFlags(&g_ts.join[t], hipEventDisableTiming));
     }
@@ -508,6 +508,59 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
         if ((rc = tier_streams_init())) return rc;
         ARB_HIP(hipEventRecord(g_ts.fork, s));
     }
+    // Items above the LDS tiers (global-scratch kernel).  Its schedule items do not depend
+    // on the tier kernels, so with the tiers side by side it starts first, on a stream of
+    // its own (one 16-wave team per CU beside the tiers' teams); the pair items that the
+    // tier kernels overflow follow in a second launch after them.
+    auto launch_big_part = [&](int parts, hipStream_t bs) -> int {
+        CountArgs a;
+        a.off = dg->offsets;
+        a.idx = dg->indices;
+        a.roff = roff;
+        a.ridx = ridx;
+        a.n = n;
+        a.m = m;
+        a.k = k;
+        a.item_root = w.iroot;
+        a.item_child = w.ichild;
+        a.seg = w.seg + kBigTier;
+        a.head = w.heads + (parts & kBigSegment ? kBigTier : kBigTier + 1);
+        a.total = total;
+        a.pv = pv;
+        a.per_root = per_root;
+        a.work = work;
+        a.cycles = cycles;
+        a.root_ids = root_ids;
+        a.err = w.err;
+        a.chunk = 1;
+        a.span_max = 0;
+        a.persistent = 1;
+        a.one_item_per_team = 0;
+        a.ovf_items = w.ovf_items;
+        a.ovf_count = w.ovf_count;
+        a.ovf_cap = w.ovf_cap;
+        const BigArgs b{w.big_rows, w.big_words, w.dbig, parts};
+        const unsigned grid = (unsigned)(w.big_teams < cus ? w.big_teams : cus);
+        const int ptier = parts & kBigSegment ? kBigTier : kBigTier + 1;
+        ProfPending pp{ProfKey{ptier, k, pvm ? 1 : 0, instr ? 1 : 0}, nullptr, nullptr};
+        if (prof) {
+            if (prof_event(&pp.a) || prof_event(&pp.b)) return ARB_EHIP;
+            if (hipEventRecord(pp.a, bs) != hipSuccess) return ARB_EHIP;
+        }
+        const int r = launch_count_big(pvm, instr, a, b, grid, bs);
+        if (r) return r;
+        if (prof) {
+            if (hipEventRecord(pp.b, bs) != hipSuccess) return ARB_EHIP;
+            g_prof.pending.push_back(pp);
+        }
+        return ARB_OK;
+    };
+    if (conc && w.big_teams > 0) {
+        hipStream_t bs = g_ts.st[kNumTiers];
+        ARB_HIP(hipStreamWaitEvent(bs, g_ts.fork, 0));
+        if ((rc = launch_big_part(kBigSegment, bs))) return rc;
+        ARB_HIP(hipEventRecord(g_ts.join[kNumTiers], bs));
+    }
     for (int t = kNumTiers - 1; t >= 0; --t) {
         CountArgs a;
         a.off = dg->offsets;
@@ -570,45 +623,13 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
         }
     }
     if (w.big_teams > 0) {
-        // roots above the LDS tiers and overflowed pair items, after the tier kernels
-        // (joined into s above)
-        CountArgs a;
-        a.off = dg->offsets;
-        a.idx = dg->indices;
-        a.roff = roff;
-        a.ridx = ridx;
-        a.n = n;
-        a.m = m;
-        a.k = k;
-        a.item_root = w.iroot;
-        a.item_child = w.ichild;
-        a.seg = w.seg + kBigTier;
-        a.head = w.heads + kBigTier;
-        a.total = total;
-        a.pv = pv;
-        a.per_root = per_root;
-        a.work = work;
-        a.cycles = cycles;
-        a.root_ids = root_ids;
-        a.err = w.err;
-        a.chunk = 1;
-        a.span_max = 0;
-        a.persistent = 1;
-        a.one_item_per_team = 0;
-        a.ovf_items = w.ovf_items;
-        a.ovf_count = w.ovf_count;
-        a.ovf_cap = w.ovf_cap;
-        const BigArgs b{w.big_rows, w.big_words, w.dbig};
-        const unsigned grid = (unsigned)(w.big_teams < cus ? w.big_teams : cus);
-        ProfPending pp{ProfKey{kBigTier, k, pvm ? 1 : 0, instr ? 1 : 0}, nullptr, nullptr};
-        if (prof) {
-            if ((rc = prof_event(&pp.a)) || (rc = prof_event(&pp.b))) return rc;
-            ARB_HIP(hipEventRecord(pp.a, s));
-        }
-        if ((rc = launch_count_big(pvm, instr, a, b, grid, s))) return rc;
-        if (prof) {
-            ARB_HIP(hipEventRecord(pp.b, s));
-            g_prof.pending.push_back(pp);
+        if (conc) {
+            // the overflowed pair items, which the tier kernels appended
+            ARB_HIP(hipStreamWaitEvent(s, g_ts.join[kNumTiers], 0));
+            if ((rc = launch_big_part(kBigOverflow, s))) return rc;
+        } else {
+            // roots above the LDS tiers, then the overflowed pair items, after the tiers
+            if ((rc = launch_big_part(kBigSegment | kBigOverflow, s))) return rc;
         }
     }
     k_finish<<<1, 64, 0, s>>>(w.err, total);

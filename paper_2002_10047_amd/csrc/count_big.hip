@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
     const uint64_t below = lanes_below_mask();
     uint32_t *grow = b.rows + (int64_t)blockIdx.x * b.team_words;
     const int64_t beg = a.seg[0], end = a.seg[1];
-    const int64_t nseg = end - beg;
+    const int64_t nseg = b.parts & kBigSegment ? end - beg : 0;
     unsigned long long acc = 0;
     while (true) {
         __syncthreads();
@@ -289,6 +289,7 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
         if (q < nseg) {
             it = beg + q;
         } else {
+            if (!(b.parts & kBigOverflow)) break;
             const int64_t o = q - nseg;
             const int64_t novf = (int64_t)*a.ovf_count;
             if (o >= (novf < a.ovf_cap ? novf : a.ovf_cap)) break;

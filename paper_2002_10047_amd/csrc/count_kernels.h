@@ -1117,11 +1117,14 @@ inline size_t tier_block_lds(int tier, bool pv, int lmax) {
 // item, S and its hash in LDS, the bit rows of G[S] in a per-team slice of global scratch
 // (L2 / Infinity Cache resident), up to kBigMax vertices.
 constexpr int kBigMax = 4096;
+constexpr int kBigSegment = 1;     // a launch takes the schedule's items of the big tier
+constexpr int kBigOverflow = 2;    // ... and / or the pair items the tier kernels overflowed
 struct BigArgs {
     uint32_t *rows;        // scratch: teams x team_words words
     int64_t team_words;
     int dbig;              // roots with ARB_MAX_LOCAL < d+ <= dbig and overflowed pair
                            // sets up to dbig take this path
+    int parts;             // kBigSegment | kBigOverflow
 };
 
 // Largest out-degree the peel can produce on m edges: d(d+1) <= 2(2+eps)m, so at eps = 1
