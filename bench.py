@@ -555,14 +555,23 @@ def main():
     g = gg.config_graph("c2")
     off20, idx20 = arb.to_device_csr(g)
     w20 = Workload(arb, torch, "rmat20", g.n, off20, idx20, [3, 4, 5], a.eps, False, a, "rmat20")
+    arb.arb_profile_enable(True)
     ms20, tot20 = w20.timed(main_name, a.steps, a.warmup)
+    prof20 = [e for e in arb.arb_profile_read() if not e["instrumented"]]
+    arb.arb_profile_enable(False)
     sch = w20.compare_schedules(main_name, ms20, tot20, a.steps, a.warmup)
     t_or, t_k = w20.phases(main_name)
+    # every tier kernel's fractions side by side (the k = 5 tiers run concurrently, so a
+    # kernel's own fraction understates the machine's), and the whole count of each k
+    rf20, ph20 = roofline(arb, np, torch, w20.o, [3, 4, 5], False, w20.opts[main_name], prof20, "rmat20_k345")
     out["rmat20_k345"] = {"n": g.n, "m": g.m, "totals": {str(k): v for k, v in tot20.items()}, "orient_s": t_or,
                           "oriented_edges_per_s": g.m / t_or, "count_s": {str(k): t for k, t in t_k.items()},
                           "step_ms": sch["ms_per_step"], "value": sum(tot20.values()) / (ms20 / 1e3),
                           "learned_gain_vs_degree": sch["learned_gain_vs_degree"],
-                          "learned_gain_vs_plain": sch["learned_gain_vs_plain"]}
+                          "learned_gain_vs_plain": sch["learned_gain_vs_plain"], "roofline": rf20,
+                          "per_k_fracs": {str(k): {"alu": u["alu"] / t_k[k] / 1e12 / PEAK_ALU_TOPS,
+                                                   "hbm": u["hbm"] / t_k[k] / 1e9 / PEAK_HBM_GBS}
+                                          for k, u in ph20.items()}}
 
     if not a.no_studies:
         studies(arb, gg, torch, g, off20, idx20, w20, tot20, a, out)

@@ -24,6 +24,32 @@ namespace arb {
 constexpr int kBigGatherUnroll = 8;   // independent 4-byte list loads in flight per lane
 constexpr int kWaveFrames = ARB_MAX_K - 4;
 
+// The team's bit rows in global scratch.  Symmetric rows (per-vertex mode) are full rows
+// of RS words (RS: ceil(d / 32) rounded up to a multiple of 4, so that rows are 16-byte
+// aligned).  Upper rows hold no bit below their own vertex, so they are stored from the
+// 16-byte vector holding their own word on: row x keeps vectors x / 128 .. RS / 4 - 1, and
+// the rows are packed one after another (half the scratch of full rows, which keeps more
+// of a team's rows in the L2).
+template <bool FULL>
+struct BigRows {
+    uint32_t *g;
+    int RS;
+    // words before row x: 4 * sum_{i < x} (RS / 4 - i / 128)
+    __device__ __forceinline__ int64_t start(int x) const {
+        if constexpr (FULL) {
+            return (int64_t)x * RS;
+        } else {
+            const int64_t q = x >> 7, r = x & 127;
+            return 4 * ((int64_t)x * (RS >> 2) - (64 * q * (q - 1) + r * q));
+        }
+    }
+    // first stored word of row x
+    __device__ __forceinline__ int lo(int x) const { return FULL ? 0 : 4 * (x >> 7); }
+    // row x as an array indexed by word (only words lo(x) .. RS - 1 are stored)
+    __device__ __forceinline__ uint32_t *row(int x) const { return g + start(x) - lo(x); }
+    __device__ __forceinline__ int64_t words(int d) const { return start(d); }
+};
+
 template <bool PV>
 struct BigLds {
     static constexpr int TW = 16;
@@ -38,26 +64,33 @@ struct BigLds {
         uint32_t ring[TW][RING];    // pair phase at k - 1 = 3: (x << 16 | y) per pair
         ListEnt lt[TW][64];         // second level
     } q;
+    // upper rows are built in LDS a window of rows at a time (row i's bits all come from
+    // the list N+(S[i]), so a window needs only its own lists) and then copied out
+    static constexpr int WINW = PV ? 1 : 12288;
+    uint32_t win[WINW];
     unsigned long long red[TW];
     int d;
     int pop;
     int next;
 };
 static_assert((1 << BigLds<true>::HB) == BigLds<true>::HS, "hash size");
-static_assert(sizeof(BigLds<true>) <= 160 * 1024, "big-item LDS");
+static_assert(sizeof(BigLds<true>) <= 160 * 1024 && sizeof(BigLds<false>) <= 160 * 1024, "big-item LDS");
 
-// second level: lists N+(S[i]) for i = wv, wv + 16, ... as one stream per wave
-template <bool PV, bool SYM, class Lds>
-__device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int32_t first, int32_t last, int wv,
-                           int lane, uint32_t *grow, int W, unsigned long long &mine, unsigned long long &words) {
+// second level: lists N+(S[i]) for i = rbeg + wv, rbeg + wv + 16, ... < rend as one stream
+// per wave; with WIN the found bits go to the LDS window of rows rbeg .. rend - 1, else
+// to the global rows with atomics
+template <bool PV, bool SYM, bool WIN, class Lds>
+__device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int rbeg, int rend, int need, int32_t first,
+                           int32_t last, int wv, int lane, const BigRows<PV> &rows, unsigned long long &mine,
+                           unsigned long long &words) {
     AS3<ListEnt> *lt = T->q.lt[wv];
-    const int nl = wv < d ? (d - wv + Lds::TW - 1) / Lds::TW : 0;
+    const int nl = rbeg + wv < rend ? (rend - rbeg - wv + Lds::TW - 1) / Lds::TW : 0;
     for (int gb = 0; gb < nl; gb += 64) {
         const int t = gb + lane;
         int64_t s = 0, e = 0;
         int row = 0;
         if (t < nl) {
-            row = wv + Lds::TW * t;
+            row = rbeg + wv + Lds::TW * t;
             const int32_t u = T->S[row];
             s = a.off[u];
             e = a.off[u + 1];
@@ -109,9 +142,11 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int
                         lds_add(&T->cnt[j], 1ull);
                         lds_add(&T->cnt[i], 1ull);
                     }
+                } else if constexpr (WIN) {
+                    lds_or(&T->win[(i - rbeg) * rows.RS + (j >> 5)], 1u << (j & 31));
                 } else {
-                    atomicOr(&grow[(int64_t)i * W + (j >> 5)], 1u << (j & 31));
-                    if constexpr (SYM) atomicOr(&grow[(int64_t)j * W + (i >> 5)], 1u << (i & 31));
+                    atomicOr(&rows.row(i)[j >> 5], 1u << (j & 31));          // j > i
+                    if constexpr (SYM) atomicOr(&rows.row(j)[i >> 5], 1u << (i & 31));
                 }
             }
         }
@@ -120,22 +155,46 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int d, int need, int
 }
 
 // One pair (x, y), x < y, at k - 1 = 3: popcount(row x AND row y) over the members above y
-// (the words at or above y's word; rows may be symmetric); per-vertex: each common member
-// z above y gains 1, x and y gain the pair's count
+// (the words at or above y's word; rows may be symmetric), read as 16-byte vectors from the
+// one holding y's word (words past ceil(d / 32) are zero); per-vertex: each
+// common member z above y gains 1, x and y gain the pair's count
 template <bool PV, class Lds>
-__device__ __forceinline__ unsigned big_pair(AS3<Lds> *T, const uint32_t *grow, int W, int x, int y) {
-    const uint32_t *rx = grow + (int64_t)x * W;
-    const uint32_t *ry = grow + (int64_t)y * W;
+__device__ __forceinline__ unsigned pair_words(AS3<Lds> *T, int w0, uint32_t t0, uint32_t t1, uint32_t t2,
+                                               uint32_t t3) {
+    uint32_t t[4] = {t0, t1, t2, t3};
     unsigned c = 0;
-    for (int w = y >> 5; w < W; ++w) {
-        uint32_t t = rx[w] & ry[w] & gtmask(y, w);
-        c += __popc(t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c += __popc(t[q]);
         if constexpr (PV) {
-            while (t) {
-                lds_add(&T->cnt[w * 32 + __ffs(t) - 1], 1ull);
-                t &= t - 1;
+            while (t[q]) {
+                lds_add(&T->cnt[(w0 + q) * 32 + __ffs(t[q]) - 1], 1ull);
+                t[q] &= t[q] - 1;
             }
         }
+    }
+    return c;
+}
+
+template <bool PV, class Lds>
+__device__ __forceinline__ unsigned big_pair(AS3<Lds> *T, const BigRows<PV> &rows, int x, int y) {
+    const uint4 *rx = reinterpret_cast<const uint4 *>(rows.row(x));
+    const uint4 *ry = reinterpret_cast<const uint4 *>(rows.row(y));
+    const int v0 = y >> 7, vn = rows.RS >> 2;
+    // the vector holding y's word: only the members above y; the ones after it whole, two
+    // vectors of each row in flight at a time
+    uint4 ax = rx[v0], ay = ry[v0];
+    unsigned c = pair_words<PV, Lds>(T, 4 * v0, ax.x & ay.x & gtmask(y, 4 * v0), ax.y & ay.y & gtmask(y, 4 * v0 + 1),
+                                     ax.z & ay.z & gtmask(y, 4 * v0 + 2), ax.w & ay.w & gtmask(y, 4 * v0 + 3));
+    for (int v = v0 + 1; v < vn; v += 2) {
+        const uint4 a0 = rx[v], b0 = ry[v];
+        uint4 a1 = make_uint4(0u, 0u, 0u, 0u), b1 = a1;
+        if (v + 1 < vn) {
+            a1 = rx[v + 1];
+            b1 = ry[v + 1];
+        }
+        c += pair_words<PV, Lds>(T, 4 * v, a0.x & b0.x, a0.y & b0.y, a0.z & b0.z, a0.w & b0.w);
+        c += pair_words<PV, Lds>(T, 4 * v + 4, a1.x & b1.x, a1.y & b1.y, a1.z & b1.z, a1.w & b1.w);
     }
     if constexpr (PV) {
         if (c) {
@@ -151,10 +210,11 @@ struct WSet {
     uint32_t h0, h1;
 };
 
-__device__ __forceinline__ WSet wload(const uint32_t *row, int W, int lane) {
+// words lo .. W - 1 of a row (the words below lo are zero)
+__device__ __forceinline__ WSet wload(const uint32_t *row, int lo, int W, int lane) {
     WSet r;
-    r.h0 = lane < W ? row[lane] : 0u;
-    r.h1 = lane + 64 < W ? row[lane + 64] : 0u;
+    r.h0 = lane < W && lane >= lo ? row[lane] : 0u;
+    r.h1 = lane + 64 < W && lane + 64 >= lo ? row[lane + 64] : 0u;
     return r;
 }
 
@@ -196,7 +256,7 @@ __device__ __forceinline__ bool wempty(WSet a) { return __ballot((a.h0 | a.h1) !
 // per-vertex credit at a node needing two more vertices with set I: each z in I gains its
 // neighbours in I (symmetric rows); returns the lane's share of the node's cliques
 template <bool PV, bool INSTR, class Lds>
-__device__ __forceinline__ unsigned long long wleaf(AS3<Lds> *T, const uint32_t *grow, int W, WSet I, int lane,
+__device__ __forceinline__ unsigned long long wleaf(AS3<Lds> *T, const BigRows<PV> &rows, int W, WSet I, int lane,
                                                     unsigned long long &nodes) {
     if constexpr (INSTR) nodes += wpopc(I);
     unsigned long long c = 0;
@@ -204,7 +264,7 @@ __device__ __forceinline__ unsigned long long wleaf(AS3<Lds> *T, const uint32_t 
     while (true) {
         const int z = wpop(R, lane);
         if (z < 0) break;
-        const WSet rz = wload(grow + (int64_t)z * W, W, lane);
+        const WSet rz = wload(rows.row(z), rows.lo(z), W, lane);
         c += wpopc(wand(R, rz));                          // R: I's members above z
         if constexpr (PV) {
             const unsigned long long az = wave_sum((unsigned long long)wpopc(wand(I, rz)));
@@ -217,11 +277,11 @@ __device__ __forceinline__ unsigned long long wleaf(AS3<Lds> *T, const uint32_t 
 // L-cliques (L >= 2) inside the wave's set J: frames of a private stack hold the untaken
 // members of every level above the last two; returns the lane's share
 template <bool PV, bool INSTR, class Lds>
-__device__ __attribute__((noinline)) unsigned long long wdfs(AS3<Lds> *T, const uint32_t *grow, int W, WSet J,
+__device__ __attribute__((noinline)) unsigned long long wdfs(AS3<Lds> *T, const BigRows<PV> rows, int W, WSet J,
                                                               int L, int lane, unsigned long long *nodes_out) {
     unsigned long long nodes = 0;
     if (L == 2) {
-        const unsigned long long c = wleaf<PV, INSTR, Lds>(T, grow, W, J, lane, nodes);
+        const unsigned long long c = wleaf<PV, INSTR, Lds>(T, rows, W, J, lane, nodes);
         if constexpr (INSTR) *nodes_out += nodes;
         return c;
     }
@@ -245,11 +305,11 @@ __device__ __attribute__((noinline)) unsigned long long wdfs(AS3<Lds> *T, const 
             C[f] += c;
             continue;
         }
-        const WSet K = wand(R[f], wload(grow + (int64_t)z * W, W, lane));   // R: members above z
+        const WSet K = wand(R[f], wload(rows.row(z), rows.lo(z), W, lane));  // R: members above z
         const int lvl = L - f;                  // vertices to choose in frame f, z included
         if (wempty(K)) continue;
         if (lvl == 3) {
-            const unsigned long long c = wleaf<PV, INSTR, Lds>(T, grow, W, K, lane, nodes);
+            const unsigned long long c = wleaf<PV, INSTR, Lds>(T, rows, W, K, lane, nodes);
             if constexpr (PV) {
                 const unsigned long long t = wave_sum(c);
                 if (lane == 0 && t) lds_add(&T->cnt[z], t);
@@ -348,11 +408,12 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
         const int d = T->d;
         if (d < need || d == 0) continue;          // no clique fits
         const int W = (d + 31) / 32;
+        const BigRows<PV> rows{grow, (W + 3) & ~3};
         for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
         if constexpr (PV)
             for (int i = tlid; i < d; i += TT) T->cnt[i] = 0ull;
-        if (need >= 3)
-            for (int64_t i = tlid; i < (int64_t)d * W; i += TT) grow[i] = 0u;
+        if (PV && need >= 3)
+            for (int64_t i = tlid; i < rows.words(d); i += TT) grow[i] = 0u;
         if (tlid == 0) T->next = TW;
         // the zeroed rows must reach L2 before any wave's atomics
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -365,12 +426,30 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
             if (tlid == 0) mine = (unsigned long long)d;
             if constexpr (PV)
                 for (int i = tlid; i < d; i += TT) T->cnt[i] = 1ull;
+        } else if (PV || need == 2) {
+            big_gather<PV, PV, false, Lds>(T, a, 0, d, need, first, last, wv, lane, rows, mine, words);
         } else {
-            big_gather<PV, PV, Lds>(T, a, d, need, first, last, wv, lane, grow, W, mine, words);
+            // upper rows, a window of rows at a time: built in LDS, then copied to the
+            // team's packed rows (a wave per row, the row's stored words)
+            const int RS = rows.RS;
+            const int Rw = Lds::WINW / RS;              // RS <= 128: at least 96 rows
+            for (int r0 = 0; r0 < d; r0 += Rw) {
+                const int r1 = r0 + Rw < d ? r0 + Rw : d;
+                for (int i = tlid; i < (r1 - r0) * RS; i += TT) T->win[i] = 0u;
+                __syncthreads();
+                big_gather<PV, false, true, Lds>(T, a, r0, r1, need, first, last, wv, lane, rows, mine, words);
+                __syncthreads();
+                for (int i = r0 + wv; i < r1; i += TW) {
+                    uint32_t *gr = rows.row(i);
+                    const AS3<uint32_t> *wr = &T->win[(i - r0) * RS];
+                    for (int w = rows.lo(i) + lane; w < RS; w += 64) gr[w] = wr[w];
+                }
+                __syncthreads();
+            }
         }
         if (need >= 3) {
-            // the rows were set by global atomics of all waves: complete them, then read
-            // them past this CU's L1
+            // the rows were written by all waves (global atomics, or stores of the LDS
+            // windows): complete them, then read them past this CU's L1
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -382,9 +461,10 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
                 unsigned head = 0, tail = 0;
                 int x = wv;
                 while (x < d) {
-                    const uint32_t *rx = grow + (int64_t)x * W;
+                    const uint32_t *rx = rows.row(x);
+                    const int xlo = rows.lo(x);
                     for (int cw = 0; cw < W; cw += 64) {
-                        uint32_t bits = cw + lane < W ? rx[cw + lane] : 0u;
+                        uint32_t bits = cw + lane < W && cw + lane >= xlo ? rx[cw + lane] : 0u;
                         if constexpr (PV) bits &= gtmask(x, cw + lane);      // symmetric rows
                         const unsigned c = __popc(bits);
                         unsigned pre = c;
@@ -407,7 +487,7 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
                             const unsigned stop = all ? stop_all : head + Lds::RING;
                             while (stop - head >= 64) {
                                 const uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                                mine += big_pair<PV, Lds>(T, grow, W, (int)(p >> 16), (int)(p & 0xffffu));
+                                mine += big_pair<PV, Lds>(T, rows, (int)(p >> 16), (int)(p & 0xffffu));
                                 if constexpr (INSTR) nodes += 1;
                                 head += 64;
                             }
@@ -422,7 +502,7 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
                 }
                 if (tail != head && lane < (int)(tail - head)) {
                     const uint32_t p = ring[(head + lane) & (Lds::RING - 1)];
-                    mine += big_pair<PV, Lds>(T, grow, W, (int)(p >> 16), (int)(p & 0xffffu));
+                    mine += big_pair<PV, Lds>(T, rows, (int)(p >> 16), (int)(p & 0xffffu));
                     if constexpr (INSTR) nodes += 1;
                 }
             } else {
@@ -430,7 +510,7 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
                 // by the wave
                 int x = wv;
                 while (x < d) {
-                    WSet rx = wload(grow + (int64_t)x * W, W, lane);
+                    WSet rx = wload(rows.row(x), rows.lo(x), W, lane);
                     if constexpr (PV) rx = wabove(rx, x, lane);       // symmetric rows: members above x
                     WSet Y = rx;
                     unsigned long long cx = 0;                         // per-vertex: cliques through x
@@ -438,9 +518,9 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
                         const int y = wpop(Y, lane);
                         if (y < 0) break;
                         if constexpr (INSTR) nodes += lane == 0 ? 1ull : 0ull;
-                        WSet ry = wload(grow + (int64_t)y * W, W, lane);
+                        WSet ry = wload(rows.row(y), rows.lo(y), W, lane);
                         const WSet J = PV ? wabove(wand(rx, ry), y, lane) : wand(rx, ry);
-                        const unsigned long long c = wdfs<PV, INSTR, Lds>(T, grow, W, J, pneed, lane, &nodes);
+                        const unsigned long long c = wdfs<PV, INSTR, Lds>(T, rows, W, J, pneed, lane, &nodes);
                         mine += c;
                         if constexpr (PV) {
                             const unsigned long long t = wave_sum(c);

@@ -1140,7 +1140,8 @@ inline int64_t big_teams(int64_t m) {
     const int64_t t = m / (ARB_MAX_LOCAL + 1);
     return big_dmax(m) == 0 ? 0 : (t < 1 ? 1 : (t > 256 ? 256 : t));
 }
-inline int64_t big_team_words(int dbig) { return (int64_t)dbig * ((dbig + 31) / 32); }
+// rows of ceil(dbig / 32) words padded to a multiple of 4 (16-byte rows)
+inline int64_t big_team_words(int dbig) { return (int64_t)dbig * ((((dbig + 31) / 32) + 3) & ~3); }
 
 int launch_count_big(bool pv, bool instr, const CountArgs &a, const BigArgs &b, unsigned grid, hipStream_t s);
 
