@@ -24,6 +24,8 @@ namespace arb {
 constexpr int kBigGatherUnroll = 8;   // independent 4-byte list loads in flight per lane
 constexpr int kWaveFrames = ARB_MAX_K - 4;
 
+__device__ __forceinline__ uint32_t big_filter_hash(int32_t w) { return ((uint32_t)w * 2246822519u) >> 18; }
+
 // The team's bit rows in global scratch.  Symmetric rows (per-vertex mode) are full rows
 // of RS words (RS: ceil(d / 32) rounded up to a multiple of 4, so that rows are 16-byte
 // aligned).  Upper rows hold no bit below their own vertex, so they are stored from the
@@ -59,6 +61,11 @@ struct BigLds {
     static constexpr int RING = 128;        // per-wave pair ring, rows written in windows
     int32_t S[kBigMax];
     unsigned long long H[HS];
+    // 16384-bit filter of S (bit big_filter_hash(s) per member s): most second-level
+    // entries are no members, and a clear bit rejects one with a single LDS read instead
+    // of a hash probe sequence
+    static constexpr int FW = 512;
+    uint32_t flt[FW];
     unsigned long long cnt[PV ? kBigMax : 1];
     union {
         uint32_t ring[TW][RING];    // pair phase at k - 1 = 3: (x << 16 | y) per pair
@@ -133,6 +140,8 @@ __device__ void big_gather(AS3<Lds> *T, const CountArgs &a, int rbeg, int rend, 
             }
 #pragma unroll
             for (int q = 0; q < kBigGatherUnroll; ++q) {
+                const uint32_t h = big_filter_hash(w[q]);
+                if (!((T->flt[h >> 5] >> (h & 31u)) & 1u)) continue;
                 const int j = member_find(T, w[q], first, last, false);
                 if (j < 0) continue;
                 const int i = r[q];
@@ -410,6 +419,7 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
         const int W = (d + 31) / 32;
         const BigRows<PV> rows{grow, (W + 3) & ~3};
         for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
+        for (int i = tlid; i < Lds::FW; i += TT) T->flt[i] = 0u;
         if constexpr (PV)
             for (int i = tlid; i < d; i += TT) T->cnt[i] = 0ull;
         if (PV && need >= 3)
@@ -418,7 +428,11 @@ __global__ void __launch_bounds__(1024) k_count_big(CountArgs a, BigArgs b) {
         // the zeroed rows must reach L2 before any wave's atomics
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        for (int i = tlid; i < d; i += TT) hash_insert(T, (uint32_t)T->S[i], (uint32_t)i);
+        for (int i = tlid; i < d; i += TT) {
+            hash_insert(T, (uint32_t)T->S[i], (uint32_t)i);
+            const uint32_t h = big_filter_hash(T->S[i]);
+            lds_or(&T->flt[h >> 5], 1u << (h & 31u));
+        }
         __syncthreads();
         const int32_t first = T->S[0], last = T->S[d - 1];
         unsigned long long mine = 0, words = 0, nodes = 0;

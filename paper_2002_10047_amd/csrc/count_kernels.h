@@ -102,15 +102,13 @@ struct TeamLds {
     using RingT = typename std::conditional<CR, uint16_t, uint32_t>::type;
     static constexpr int SPAN = TierCfg<W, PV, 1>::SPAN;
     static constexpr int SW = SPAN > 0 ? SPAN / 32 : 1;
-    // the 64-tier (always hash mode) screens its second-level entries with a member filter;
-    // in the larger tiers it measured slower (bitmap mode is as cheap, and their sets fill
-    // more of the filter)
-    static constexpr bool FILTER = W == 2;
+    // in hash mode (always in the 64-tier) the second-level entries are screened with a
+    // member filter before the hash probe; the id-range bitmap is as cheap as the filter
     int32_t S[D];
     unsigned long long H[HS];
     uint32_t bm[SW];        // member bitmap over ids first .. first + SPAN - 1
     uint16_t pre[SW];       // local id of the first member in each bitmap word
-    uint32_t flt[FILTER ? 64 : 1];   // 2048-bit filter of S (bit filter_hash(s) per member s)
+    uint32_t flt[64];       // 2048-bit filter of S (bit filter_hash(s) per member s)
     alignas(16) uint32_t rows[D * RS];
     unsigned long long cnt[PV ? D : 1];
     union {
@@ -668,7 +666,7 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
                                              int32_t first, int32_t last, bool bmode, int wv, int lane,
                                              unsigned long long &mine, unsigned long long &words) {
     AS3<ListEnt> *lt = T->q.lt[wv];
-    const uint32_t fw = Lds::FILTER ? T->flt[lane] : 0u;   // this lane's word of the member filter
+    const uint32_t fw = bmode ? 0u : T->flt[lane];          // this lane's word of the member filter
     const int nl = g0 < d ? (d - g0 + gstep - 1) / gstep : 0;
     for (int gb = 0; gb < nl; gb += 64) {
         const int t = gb + lane;
@@ -718,7 +716,7 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
                 }
             }
             bool maybe[GU];
-            if (!Lds::FILTER || bmode) {
+            if (bmode) {
 #pragma unroll
                 for (int q = 0; q < GU; ++q) maybe[q] = true;
             } else {
@@ -835,7 +833,7 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
     } else {
         for (int i = tlid; i < Lds::HS; i += TT) T->H[i] = kEmpty;
     }
-    if (Lds::FILTER)
+    if (!bmode)
         for (int i = tlid; i < 64; i += TT) T->flt[i] = 0u;
     if (need >= 3)
         for (int i = tlid; i < d * Lds::RS; i += TT) T->rows[i] = 0u;
@@ -850,13 +848,12 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
             if (i == 0 || ((uint32_t)(T->S[i - 1] - first) >> 5) != (o >> 5)) T->pre[o >> 5] = (uint16_t)i;
         }
     } else {
-        for (int i = tlid; i < d; i += TT) hash_insert(T, (uint32_t)T->S[i], (uint32_t)i);
-    }
-    if (Lds::FILTER)
         for (int i = tlid; i < d; i += TT) {
+            hash_insert(T, (uint32_t)T->S[i], (uint32_t)i);
             const uint32_t h = filter_hash(T->S[i]);
             lds_or(&T->flt[h >> 5], 1u << (h & 31u));
         }
+    }
     team_sync<TW, TPB>();
 
     unsigned long long mine = 0;      // this lane's share of the item's clique count

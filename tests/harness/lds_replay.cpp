@@ -53,7 +53,6 @@ uint32_t gtmask(int z, int w) {
 struct Team {
     // capacities as the kernel's TeamLds<W, PV = true, TW> and TierCfg<W, true, LMAX>
     int W, TW, D, Q, RS, HS, HB, SPAN, SW, RING;
-    bool FILTER;
     Arr<int32_t> S;
     Arr<uint64_t> H;
     Arr<uint32_t> bm;
@@ -68,8 +67,8 @@ struct Team {
         : W(W_), TW(W_ == 2 ? 1 : (W_ <= 8 ? 4 : 8)), D(32 * W_), Q(W_ >= 16 ? 4 : 1),
           RS((W_ / Q) % 2 == 1 ? W_ : W_ + Q), HS(pow2_at_least(D <= 128 ? 4 * D : 2 * D)), HB(__builtin_ctz(HS)),
           SPAN(W_ == 2 ? 0 : (W_ == 4 ? 1 << 16 : (W_ <= 16 ? 1 << 15 : 1 << 14))), SW(SPAN > 0 ? SPAN / 32 : 1),
-          RING(pow2_at_least(D + 64)), FILTER(W_ == 2), S("S", D), H("H", HS), bm("bm", SW), pre("pre", SW),
-          flt("flt", FILTER ? 64 : 1), rows("rows", (long)D * RS), cnt("cnt", D), ring("ring", (long)TW * RING),
+          RING(pow2_at_least(D + 64)), S("S", D), H("H", HS), bm("bm", SW), pre("pre", SW),
+          flt("flt", 64), rows("rows", (long)D * RS), cnt("cnt", D), ring("ring", (long)TW * RING),
           lt_end("lt", (long)TW * 64), lt_delta("lt", (long)TW * 64), lt_row("lt", (long)TW * 64) {}
 };
 
@@ -186,7 +185,7 @@ uint64_t process_root(Team &T, const Graph &g, int k, int32_t root, int span_max
     } else {
         for (int i = 0; i < T.HS; ++i) T.H[i] = ~0ull;
     }
-    if (T.FILTER)
+    if (!bmode)
         for (int i = 0; i < 64; ++i) T.flt[i] = 0u;
     if (need >= 3)
         for (long i = 0; i < (long)d * T.RS; ++i) T.rows[i] = 0u;
@@ -208,7 +207,7 @@ uint64_t process_root(Team &T, const Graph &g, int k, int32_t root, int span_max
             }
         }
     }
-    if (T.FILTER)
+    if (!bmode)
         for (int i = 0; i < d; ++i) {
             const uint32_t h = filter_hash(T.S[i]);
             T.flt[h >> 5] |= 1u << (h & 31u);
@@ -249,7 +248,7 @@ uint64_t process_root(Team &T, const Graph &g, int k, int32_t root, int span_max
                     if (q < 0 || q >= g.m) { fprintf(stderr, "LDS replay: list entry %ld outside the graph\n", (long)q); abort(); }
                     const int32_t w = g.idx[q];
                     const int i = T.lt_row[wv * 64 + c];
-                    if (T.FILTER && !bmode) {
+                    if (!bmode) {
                         const uint32_t h = filter_hash(w);
                         if (!((T.flt[h >> 5] >> (h & 31u)) & 1u)) continue;
                     }
