@@ -328,7 +328,9 @@ def roofline(arb, np, torch, o, ks, pv, opts_of_k, prof, workload):
                         "fracs": fr}
         log(f"  {sym}: {v['launches']} launches, avg {v['ms'] / v['launches']:.3f} ms ({'; '.join(v['parts'])}), "
             f"HBM {fr['hbm']:.2%}, ALU {fr['alu']:.2%}, LDS {fr['lds']:.2%}")
-        if best is None or v["ms"] > best[1]["ms"]:
+        # a launch that processed no item (the global-scratch kernel on a graph without
+        # large roots) only waited for CUs beside the tiers: never the dominant kernel
+        if v["hbm"] + v["alu"] + v["lds"] > 0 and (best is None or v["ms"] > best[1]["ms"]):
             best = (sym, v, fr)
     out = None
     if best:
@@ -344,7 +346,8 @@ def roofline(arb, np, torch, o, ks, pv, opts_of_k, prof, workload):
                "measured": None if mc is None else {k: mc.get(k) for k in ("valu_issue_frac", "valu_insts",
                                                                            "lds_insts", "avg_ms")},
                "launch_ms": v["ms"] / v["launches"], "algorithmic_per_launch": per, "fracs": fr,
-               "rule": "the counting kernel with the largest total time over the timed steps",
+               "rule": "the counting kernel with the largest total time over the timed steps (kernels that "
+                       "processed no item excluded)",
                "peaks_measured": peaks, "kernels": kernels}
     return out, phase
 
