@@ -58,6 +58,20 @@ __global__ void k_u64_fill(unsigned long long *p, unsigned long long v, int64_t 
         p[i] = v;
 }
 
+__global__ void k_count_reset(unsigned long long *total, int *err, int *heads, int64_t *seg,
+                              unsigned long long *ovf_count) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        *total = 0ull;
+        *ovf_count = 0ull;
+    }
+    if (t < 4) err[t] = 0;
+    if (t < 16) {
+        heads[t] = 0;
+        seg[t] = 0;
+    }
+}
+
 __global__ void k_finish(const int32_t *err, unsigned long long *total) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && *err) *total = ~0ull;
 }
@@ -455,20 +469,20 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
     }
     if (k == 1) { k_count_k1<<<gb, 256, 0, s>>>(n, total, pv); ARB_CHECK_LAUNCH(); return ARB_OK; }
     if (k == 2) { k_count_k2<<<gb, 256, 0, s>>>(n, dg->offsets, dg->indices, total, pv); ARB_CHECK_LAUNCH(); return ARB_OK; }
-    k_u64_fill<<<1, 64, 0, s>>>(total, 0ull, 1);
-    ARB_CHECK_LAUNCH();
     // roots scheduled: every vertex, or the listed ones
     const int64_t ns = root_ids ? nroots : n;
     const unsigned gs = grid_for(ns, 256, 4096);
-    if (ns == 0) return ARB_OK;
+    if (ns == 0) {
+        k_u64_fill<<<1, 64, 0, s>>>(total, 0ull, 1);
+        ARB_CHECK_LAUNCH();
+        return ARB_OK;
+    }
 
     Carver cv(ws);
     CountWs w;
     carve_count(cv, n, mw, k, &w);
-    if ((rc = fill_i32(w.err, 0, 4, s))) return rc;
-    if ((rc = fill_i32(w.heads, 0, 16, s))) return rc;
-    if ((rc = fill_i64(w.seg, 0, 16, s))) return rc;
-    k_u64_fill<<<1, 64, 0, s>>>(w.ovf_count, 0ull, 1);
+    // the total, error flags, queue heads, segments and overflow count, in one launch
+    k_count_reset<<<1, 64, 0, s>>>(total, w.err, w.heads, w.seg, w.ovf_count);
     ARB_CHECK_LAUNCH();
 
     const bool learned = opts.schedule == ARB_SCHED_LEARNED && !work;
@@ -540,7 +554,9 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
         a.ovf_count = w.ovf_count;
         a.ovf_cap = w.ovf_cap;
         const BigArgs b{w.big_rows, w.big_words, w.dbig, parts};
-        const unsigned grid = (unsigned)(w.big_teams < cus ? w.big_teams : cus);
+        int64_t bteams = w.big_teams < cus ? w.big_teams : cus;
+        if (parts & kBigSegment && ns * 64 < bteams) bteams = ns * 64;      // as for the tiers
+        const unsigned grid = (unsigned)(bteams > 0 ? bteams : 1);
         const int ptier = parts & kBigSegment ? kBigTier : kBigTier + 1;
         ProfPending pp{ProfKey{ptier, k, pvm ? 1 : 0, instr ? 1 : 0}, nullptr, nullptr};
         if (prof) {
@@ -600,6 +616,11 @@ int arb::count_with_roots(const arb_ocsr *dg, int k, uint64_t *total_dev, uint64
             if (per_cu > opts.persist_blocks_per_cu) per_cu = opts.persist_blocks_per_cu;
             if (per_cu < 1) per_cu = 1;
             grid = (unsigned)(cus * per_cu);
+            // a few scheduled roots (the peels' rounds) need few teams: a persistent grid
+            // of empty teams costs ~0.1 ms a launch.  A root gives at most 64 items here
+            // (split parts) unless it becomes pair items, which the teams still drain.
+            const int64_t cap = (ns * 64 + tpb - 1) / tpb;
+            if (cap < (int64_t)grid) grid = (unsigned)(cap > 0 ? cap : 1);
         }
         hipStream_t ls = s;
         if (conc) {

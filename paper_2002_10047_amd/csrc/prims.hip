@@ -110,6 +110,29 @@ __global__ void k_scan_apply(const int64_t *in, int64_t *out, int64_t n, const i
     }
 }
 
+// n <= one tile: the whole exclusive scan and the total (out[n]) in one block
+__global__ void k_scan_single(const int64_t *in, int64_t *out, int64_t n) {
+    __shared__ int64_t lw[kScanBlock / 64];
+    const int64_t base = (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t j = base + i;
+        v[i] = j < n ? in[j] : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(s, lw, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t j = base + i;
+        if (j < n) out[j] = ex;
+        ex += v[i];
+    }
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
 size_t scan_workspace(int64_t n) {
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;
     return (size_t)(ntiles + 1) * sizeof(int64_t) + 256;
@@ -123,6 +146,11 @@ int exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, void *ws, hip
         return ARB_OK;
     }
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles == 1) {
+        k_scan_single<<<1, kScanBlock, 0, s>>>(in, out, n);
+        ARB_CHECK_LAUNCH();
+        return ARB_OK;
+    }
     // Blocked layout inside k_scan_apply (thread-contiguous runs) differs from the
     // strided one in k_scan_reduce, but both cover exactly one tile per block.
     k_scan_reduce<<<(unsigned)ntiles, kScanBlock, 0, s>>>(in, n, partial);
