@@ -71,7 +71,8 @@ typedef struct {
 
 /* ---------------------------------------------------------------- orientation */
 
-/* Bytes of workspace arb_orient needs for a graph with n vertices and nnz entries. */
+/* Bytes of workspace arb_orient needs for a graph with n vertices and nnz entries
+ * (O(n) plus 4 bytes per entry). */
 size_t arb_orient_workspace(int64_t n, int64_t nnz);
 
 /*

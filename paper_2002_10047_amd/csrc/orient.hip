@@ -405,7 +405,7 @@ __global__ void k_rank_scatter(int64_t n, const int32_t *inv, int32_t *rank) {
 // groups' short rows.
 // Number of neighbours of higher rank, stored at the vertex's rank.
 __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *rank,
-                            int64_t *outdeg) {
+                            int64_t *outdeg, int32_t *arc_rank) {
     const int lane = threadIdx.x & 63, sl = lane & 15;
     int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
@@ -421,7 +421,11 @@ __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, c
             heavy = !light;
         }
         if (light)
-            for (int64_t p = b + sl; p < e; p += 16) c += rank[idx[p]] > rv;
+            for (int64_t p = b + sl; p < e; p += 16) {
+                const int32_t r = rank[idx[p]];
+                arc_rank[p] = r;
+                c += r > rv;
+            }
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) c += __shfl_xor(c, o, 16);
         if (light && sl == 0) outdeg[rv] = c;
@@ -437,7 +441,13 @@ __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, c
 #pragma unroll
                 for (int q = 0; q < 4; ++q) u[q] = p0 + 64 * q < he ? idx[p0 + 64 * q] : -1;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) hc += u[q] >= 0 && rank[u[q]] > hr;
+                for (int q = 0; q < 4; ++q) {
+                    if (u[q] >= 0) {
+                        const int32_t r = rank[u[q]];
+                        arc_rank[p0 + 64 * q] = r;
+                        hc += r > hr;
+                    }
+                }
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) hc += __shfl_xor(hc, o, 64);
@@ -448,7 +458,7 @@ __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, c
 
 // Write the higher-ranked neighbours' ranks into the row of the vertex's rank (order of
 // the input row; sorted afterwards).
-__global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *rank,
+__global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *arc_rank, const int32_t *rank,
                            const int64_t *ooff, int32_t *oidx) {
     const int lane = threadIdx.x & 63, sl = lane & 15, gsh = lane & 48;
     const uint32_t below16 = (1u << sl) - 1u;
@@ -476,7 +486,7 @@ __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *idx, co
         }
         int64_t wl = w;
         for (int64_t q = 0; q < lmax; q += 16) {
-            const int32_t ru = (q + sl < ll) ? rank[idx[b + q + sl]] : -1;
+            const int32_t ru = (q + sl < ll) ? arc_rank[b + q + sl] : -1;
             const bool keep = ru > rv;
             const uint32_t m = (uint32_t)(__ballot(keep) >> gsh) & 0xffffu;
             if (keep) oidx[wl + __popc(m & below16)] = ru;
@@ -494,10 +504,8 @@ __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *idx, co
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t p = q0 + 64 * q + lane;
-                    ru[q] = p < he ? idx[p] : -1;
+                    ru[q] = p < he ? arc_rank[p] : -1;
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) ru[q] = ru[q] >= 0 ? rank[ru[q]] : -1;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const bool keep = ru[q] > hr;
@@ -641,13 +649,14 @@ struct OrientWs {
     uint32_t *keys, *keys_alt;
     int32_t *vals, *vals_alt;
     int64_t *rs, *thr, *outdeg;
+    int32_t *arc_rank;       // rank of each arc's head, written by the counting pass of the
+                             // directing and read by the filling pass (one gather per arc)
     void *scan_ws, *radix_ws;
     int32_t *gid;            // batches: graph of each vertex
     int64_t *rs_g, *thr_g;   // batches: per-graph round sums and thresholds
 };
 
 static size_t carve_orient(Carver &c, int64_t n, int64_t nnz, OrientWs *w, int64_t G = 0) {
-    (void)nnz;
     int64_t nn = n > 0 ? n : 1;
     if (G > 0) {
         w->gid = c.take<int32_t>(nn);
@@ -668,6 +677,7 @@ static size_t carve_orient(Carver &c, int64_t n, int64_t nnz, OrientWs *w, int64
     w->rs = c.take<int64_t>(2 * 128);
     w->thr = c.take<int64_t>(128);
     w->outdeg = c.take<int64_t>(nn + 1);
+    w->arc_rank = c.take<int32_t>(nnz > 0 ? nnz : 1);
     w->scan_ws = c.take<char>(scan_workspace(nn + 1));
     w->radix_ws = c.take<char>(radix_workspace(nn));
     return c.used;
@@ -871,10 +881,10 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
     k_rank_scatter<<<gb, 256, 0, s>>>(n, w.vals, rank);
     // directing
     const unsigned g16 = grid_for(n * 16, 256, 8192);
-    k_dir_count<<<g16, 256, 0, s>>>(n, g->offsets, g->indices, rank, w.outdeg);
+    k_dir_count<<<g16, 256, 0, s>>>(n, g->offsets, g->indices, rank, w.outdeg, w.arc_rank);
     if (hipGetLastError() != hipSuccess) return ARB_EHIP;
     if ((rc = exclusive_scan_i64(w.outdeg, out->offsets, n, w.scan_ws, s))) return rc;
-    k_dir_fill<<<g16, 256, 0, s>>>(n, g->offsets, g->indices, rank, out->offsets, out->indices);
+    k_dir_fill<<<g16, 256, 0, s>>>(n, g->offsets, w.arc_rank, rank, out->offsets, out->indices);
     // rows longer than 64 are listed by the small-row sort (the rank-sort buffers are free
     // by now; counters in err[1], err[2])
     int32_t *mid_rows = w.vals_alt, *big_rows = reinterpret_cast<int32_t *>(w.keys_alt), *row_cnt = w.err + 1;
