@@ -80,7 +80,11 @@ struct ListEnt {
     int32_t pad;
 };
 
-template <int W, bool PV, int TW_>
+// Per-vertex counters of the 64-tier up to k = 10 fit 32 bits: a member lies in at most
+// C(63, 8) < 2^32 of a root's cliques.  32-bit LDS atomics need no high word.
+template <int W, int LMAX> constexpr bool cnt32() { return W == 2 && LMAX <= 7; }
+
+template <int W, bool PV, int TW_, bool C32 = false>
 struct TeamLds {
     static constexpr int D = 32 * W;             // capacity of S
     // bit rows are read with Q-word loads: 128-bit loads in the two largest tiers, 32-bit
@@ -110,7 +114,8 @@ struct TeamLds {
     uint16_t pre[SW];       // local id of the first member in each bitmap word
     uint32_t flt[64];       // 2048-bit filter of S (bit filter_hash(s) per member s)
     alignas(16) uint32_t rows[D * RS];
-    unsigned long long cnt[PV ? D : 1];
+    using CntT = typename std::conditional<C32, uint32_t, unsigned long long>::type;
+    CntT cnt[PV ? D : 1];
     union {
         RingT ring[TW][RING];       // pair phase
         ListEnt lt[TW][64];         // second level: the wave's current 64 lists
@@ -128,6 +133,9 @@ template <class L> using AS3 = __attribute__((address_space(3))) L;
 
 __device__ __forceinline__ void lds_add(AS3<unsigned long long> *p, unsigned long long v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(AS3<uint32_t> *p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void lds_or(AS3<uint32_t> *p, uint32_t v) {
     __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -751,12 +759,12 @@ __device__ __forceinline__ void gather_lists(AS3<Lds> *T, const CountArgs &a, in
 // ------------------------------------------------------------------ one work item
 
 template <int W, int LMAX, bool PV, bool INSTR>
-__device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, TierCfg<W, PV, LMAX>::TW>> *T,
+__device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, TierCfg<W, PV, LMAX>::TW, cnt32<W, LMAX>()>> *T,
                                                              const CountArgs a, int64_t it, int32_t root,
                                                              int32_t child, int tlid) {
     using Cfg = TierCfg<W, PV, LMAX>;
     constexpr int TW = Cfg::TW, TPB = Cfg::TPB;
-    using Lds = TeamLds<W, PV, TW>;
+    using Lds = TeamLds<W, PV, TW, cnt32<W, LMAX>()>;
     constexpr int TT = 64 * TW;
     const int lane = tlid & 63, wv = tlid >> 6;
     const uint64_t below = lanes_below_mask();
@@ -1007,7 +1015,7 @@ __attribute__((amdgpu_waves_per_eu(tier_min_waves<W, PV, LMAX>())))
 k_count(CountArgs a) {
     using Cfg = TierCfg<W, PV, LMAX>;
     constexpr int TW = Cfg::TW, TPB = Cfg::TPB;
-    using Lds = TeamLds<W, PV, TW>;
+    using Lds = TeamLds<W, PV, TW, cnt32<W, LMAX>()>;
     extern __shared__ __align__(16) unsigned char smem[];
     const int team = threadIdx.x / (64 * TW);
     const int tlid = threadIdx.x % (64 * TW);
@@ -1041,7 +1049,7 @@ k_count(CountArgs a) {
 template <int W, bool PV, int LMAX>
 constexpr size_t block_lds() {
     using Cfg = TierCfg<W, PV, LMAX>;
-    return ((sizeof(TeamLds<W, PV, Cfg::TW>) + 15) & ~size_t(15)) * Cfg::TPB;
+    return ((sizeof(TeamLds<W, PV, Cfg::TW, cnt32<W, LMAX>()>) + 15) & ~size_t(15)) * Cfg::TPB;
 }
 
 template <int W>
