@@ -895,6 +895,71 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
             unsigned head = 0, tail = 0;          // ring positions [head, tail) not yet taken
             const int pneed = need - 2;
             unsigned slot = 0;
+            // 64-tier, at least four vertices below each pair (k >= 7): the lanes deal
+            // triples (x, y, z), z a member of the pair's common set above both, through a
+            // second ring in the (now unused) hash table, so that the subtrees the lanes
+            // walk side by side are one level smaller and vary less than whole pair
+            // subtrees.  With three vertices below (k = 6) the extra pass costs more than
+            // the better balance gains
+            constexpr bool TRIPLES = W == 2 && !INSTR && LMAX >= 4;
+            const bool triples = TRIPLES && pneed >= 4;
+            AS3<uint32_t> *ring3 = reinterpret_cast<AS3<uint32_t> *>(&T->H[0]);
+            constexpr unsigned RING3 = 2 * Lds::HS;          // 512 entries of x | y << 6 | z << 12
+            unsigned head3 = 0, tail3 = 0;
+            auto take3 = [&](uint32_t e) {
+                const int x = (int)(e & 63u), y = (int)((e >> 6) & 63u), z = (int)(e >> 12);
+                const uint64_t K = row64(T, x) & row64(T, y) & row64(T, z) & ~((2ull << z) - 1ull);
+                Bits<W> KB;
+                KB.w[0] = (uint32_t)K;
+                KB.w[1] = (uint32_t)(K >> 32);
+                const Acc sub = dfs_dispatch<W, LMAX, PV, INSTR, Lds>(T, KB, pneed - 1);
+                if constexpr (PV) {
+                    if (sub.c) {
+                        lds_add(&T->cnt[x], sub.c);
+                        lds_add(&T->cnt[y], sub.c);
+                        lds_add(&T->cnt[z], sub.c);
+                    }
+                }
+                mine += sub.c;
+            };
+            // every lane of the wave: its pair (valid or not) goes into the triple ring; the
+            // pair is (row << 16 | member) of either row kind, and both kinds give the same
+            // set above the larger of the two
+            auto deal3 = [&](uint32_t p, bool valid) {
+                const int py = (int)(p >> 16), px = (int)(p & 0xffffu);
+                const int hi = py > px ? py : px;
+                uint64_t R = valid ? row64(T, px) & row64(T, py) & ~((2ull << hi) - 1ull) : 0ull;
+                const uint32_t base = (uint32_t)px | ((uint32_t)py << 6);
+                while (true) {
+                    const unsigned c = (unsigned)__popcll(R);
+                    unsigned pre = c;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const unsigned t = __shfl_up(pre, o, 64);
+                        if (lane >= o) pre += t;
+                    }
+                    const unsigned total = __shfl(pre, 63, 64);
+                    if (total == 0) break;
+                    const unsigned space = RING3 - (tail3 - head3);
+                    const unsigned start = pre - c;
+                    unsigned cnt = start >= space ? 0u : (c < space - start ? c : space - start);
+                    unsigned pos = tail3 + start;
+                    while (cnt) {
+                        const int z = __builtin_ctzll(R);
+                        R &= R - 1;
+                        ring3[pos & (RING3 - 1)] = base | ((uint32_t)z << 12);
+                        ++pos;
+                        --cnt;
+                    }
+                    tail3 += total < space ? total : space;
+                    wave_fence();
+                    while (tail3 - head3 >= 64) {
+                        take3(ring3[(head3 + lane) & (RING3 - 1)]);
+                        head3 += 64;
+                    }
+                    wave_fence();
+                }
+            };
             auto take = [&](uint32_t p) {
                 int pr, pm;          // the entry's row and member
                 if constexpr (Lds::CR) {
@@ -959,7 +1024,8 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
                 }
                 wave_fence();
                 while (end - head >= 64) {
-                    take(ring[(head + lane) & (Lds::RING - 1)]);
+                    if (triples) deal3(ring[(head + lane) & (Lds::RING - 1)], true);
+                    else take(ring[(head + lane) & (Lds::RING - 1)]);
                     head += 64;
                 }
                 wave_fence();
@@ -972,7 +1038,12 @@ __device__ __forceinline__ unsigned long long process_item(AS3<TeamLds<W, PV, Ti
                     xi += TW;
                 }
             }
-            if (tail != head && lane < (int)(tail - head)) take(ring[(head + lane) & (Lds::RING - 1)]);
+            if (triples) {
+                if (tail != head) deal3(ring[(head + lane) & (Lds::RING - 1)], lane < (int)(tail - head));
+                if (tail3 != head3 && lane < (int)(tail3 - head3)) take3(ring3[(head3 + lane) & (RING3 - 1)]);
+            } else if (tail != head && lane < (int)(tail - head)) {
+                take(ring[(head + lane) & (Lds::RING - 1)]);
+            }
         }
     }
 

@@ -165,6 +165,82 @@ uint64_t do_pair(Team &T, int d, int x, int y, int need) {
     return sub;
 }
 
+// The 64-tier at k >= 7 deals triples (x, y, z) through a second ring kept in the hash
+// table's LDS (512 entries): a round of 64 pairs pushes its children in lane order, as much
+// as fits, and the lanes take the ring's entries 64 at a time.
+struct Ring3 {
+    Arr<uint32_t> r;
+    unsigned head = 0, tail = 0;
+    Ring3() : r("ring3 (hash table)", 512) {}
+};
+
+uint64_t take3(Team &T, int d, uint32_t e, int pneed) {
+    const int x = (int)(e & 63u), y = (int)((e >> 6) & 63u), z = (int)(e >> 12);
+    if (x >= d || y >= d || z >= d || !(x < y && y < z)) { fprintf(stderr, "LDS replay: bad triple\n"); abort(); }
+    std::vector<uint32_t> rx(T.W), ry(T.W), rz(T.W), K(T.W);
+    load_row(T, d, x, rx);
+    load_row(T, d, y, ry);
+    load_row(T, d, z, rz);
+    for (int w = 0; w < T.W; ++w) K[w] = rx[w] & ry[w] & rz[w] & gtmask(z, w);
+    const uint64_t sub = dfs(T, d, K, pneed - 1);
+    if (sub) {
+        T.cnt[x] += sub;
+        T.cnt[y] += sub;
+        T.cnt[z] += sub;
+    }
+    return sub;
+}
+
+// one round: lanes 0..nvalid-1 hold the pairs p[lane] (row << 16 | member)
+uint64_t deal3(Team &T, int d, Ring3 &q, const uint32_t *p, int nvalid, int pneed) {
+    uint64_t out = 0;
+    uint64_t R[64];
+    uint32_t base[64];
+    for (int l = 0; l < 64; ++l) {
+        R[l] = 0;
+        base[l] = 0;
+        if (l < nvalid) {
+            const int py = (int)(p[l] >> 16), px = (int)(p[l] & 0xffffu);
+            std::vector<uint32_t> rx(T.W), ry(T.W);
+            load_row(T, d, px, rx);
+            load_row(T, d, py, ry);
+            const uint64_t jx = (uint64_t)rx[0] | ((uint64_t)rx[1] << 32), jy = (uint64_t)ry[0] | ((uint64_t)ry[1] << 32);
+            const int hi = py > px ? py : px;
+            R[l] = jx & jy & ~((2ull << hi) - 1ull);
+            base[l] = (uint32_t)px | ((uint32_t)py << 6);
+        }
+    }
+    while (true) {
+        unsigned pre[64], c[64], total = 0;
+        for (int l = 0; l < 64; ++l) {
+            c[l] = (unsigned)__builtin_popcountll(R[l]);
+            total += c[l];
+            pre[l] = total;
+        }
+        if (total == 0) break;
+        const unsigned space = 512 - (q.tail - q.head);
+        for (int l = 0; l < 64; ++l) {
+            const unsigned start = pre[l] - c[l];
+            unsigned cnt = start >= space ? 0u : (c[l] < space - start ? c[l] : space - start);
+            unsigned pos = q.tail + start;
+            while (cnt) {
+                const int z = __builtin_ctzll(R[l]);
+                R[l] &= R[l] - 1;
+                q.r[pos & 511u] = base[l] | ((uint32_t)z << 12);
+                ++pos;
+                --cnt;
+            }
+        }
+        q.tail += total < space ? total : space;
+        if (q.tail - q.head > 512u) { fprintf(stderr, "LDS replay: ring3 overrun\n"); abort(); }
+        while (q.tail - q.head >= 64) {
+            for (int l = 0; l < 64; ++l) out += take3(T, d, q.r[(q.head + l) & 511u], pneed);
+            q.head += 64;
+        }
+    }
+    return out;
+}
+
 // one root item, per-vertex mode; returns the item's count and adds to pv
 uint64_t process_root(Team &T, const Graph &g, int k, int32_t root, int span_max, uint64_t *pv) {
     g_root = root;
@@ -275,6 +351,8 @@ uint64_t process_root(Team &T, const Graph &g, int k, int32_t root, int span_max
         if (need >= 3) {
             g_item = "pair phase";
             const int pneed = need - 2;
+            const bool triples = T.W == 2 && pneed >= 4;
+            Ring3 q3;
             const bool dyn = T.TW > 1 && pneed >= 2;
             int next = T.TW;          // team row counter
             for (int wv = 0; wv < T.TW; ++wv) {
@@ -315,9 +393,15 @@ uint64_t process_root(Team &T, const Graph &g, int k, int32_t root, int span_max
                     }
                     if (end - head > (unsigned)T.RING) { fprintf(stderr, "LDS replay: ring overrun\n"); abort(); }
                     while (end - head >= 64) {
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const uint32_t p = T.ring[(long)wv * T.RING + ((head + lane) & (T.RING - 1))];
-                            mine += do_pair(T, d, (int)(p & 0xffffu), (int)(p >> 16), pneed);
+                        if (triples) {
+                            uint32_t pp[64];
+                            for (int lane = 0; lane < 64; ++lane) pp[lane] = T.ring[(long)wv * T.RING + ((head + lane) & (T.RING - 1))];
+                            mine += deal3(T, d, q3, pp, 64, pneed);
+                        } else {
+                            for (int lane = 0; lane < 64; ++lane) {
+                                const uint32_t p = T.ring[(long)wv * T.RING + ((head + lane) & (T.RING - 1))];
+                                mine += do_pair(T, d, (int)(p & 0xffffu), (int)(p >> 16), pneed);
+                            }
                         }
                         head += 64;
                     }
@@ -329,9 +413,17 @@ uint64_t process_root(Team &T, const Graph &g, int k, int32_t root, int span_max
                         xi += T.TW;
                     }
                 }
-                for (int lane = 0; lane < (int)(tail - head); ++lane) {
-                    const uint32_t p = T.ring[(long)wv * T.RING + ((head + lane) & (T.RING - 1))];
-                    mine += do_pair(T, d, (int)(p & 0xffffu), (int)(p >> 16), pneed);
+                if (triples) {
+                    uint32_t pp[64];
+                    const int nv = (int)(tail - head);
+                    for (int lane = 0; lane < 64; ++lane) pp[lane] = T.ring[(long)wv * T.RING + ((head + lane) & (T.RING - 1))];
+                    if (nv > 0) mine += deal3(T, d, q3, pp, nv, pneed);
+                    for (int lane = 0; lane < (int)(q3.tail - q3.head); ++lane) mine += take3(T, d, q3.r[(q3.head + lane) & 511u], pneed);
+                } else {
+                    for (int lane = 0; lane < (int)(tail - head); ++lane) {
+                        const uint32_t p = T.ring[(long)wv * T.RING + ((head + lane) & (T.RING - 1))];
+                        mine += do_pair(T, d, (int)(p & 0xffffu), (int)(p >> 16), pneed);
+                    }
                 }
             }
         }
