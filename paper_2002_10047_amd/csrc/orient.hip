@@ -7,6 +7,9 @@
 //   k_peel_threshold  T_r = floor(((2+eps) * S_r) / c_r) in IEEE double
 //   k_peel_mark       present v with deg <= T_r: round = r, deg_at_peel = deg (start of round)
 //   k_peel_decrement  each vertex removed in round r lowers each still-present neighbour
+//                     (push), or each vertex still present counts its neighbours removed
+//                     in round r (pull): whichever walks fewer arcs, chosen on the device
+//                     from the arc totals k_peel_mark adds up; both leave the same degrees
 // A round with c_r = 0 does nothing, so the host enqueues the proven maximum number of
 // rounds, ceil(log_{2+eps} n): every round leaves fewer than c_r/(2+eps) vertices.
 #include <math.h>
@@ -26,6 +29,7 @@ enum : int32_t {
 // rows of at most this many entries are walked by a group of 16 lanes, longer ones by a
 // whole wave
 constexpr int kGroupRow = 64;
+static_assert(kGroupRow <= 4 * 16, "a short row is four loads per lane of its 16-lane group");
 
 // ------------------------------------------------------------------ validation
 
@@ -117,25 +121,58 @@ __global__ void k_peel_threshold(int r, double eps, const int64_t *rs, int64_t *
     }
 }
 
-__global__ void k_peel_mark(int64_t n, const int32_t *deg, int32_t *rnd, int32_t *dap, int r, const int64_t *thr) {
+// arcs[2r] += row lengths of the vertices removed in round r, arcs[2r+1] += those of the
+// vertices still present after it (the arcs a push or a pull decrement would walk)
+__global__ void k_peel_mark(int64_t n, const int64_t *off, const int32_t *deg, int32_t *rnd, int32_t *dap, int r,
+                            const int64_t *thr, int64_t *arcs) {
     int64_t T = thr[r];
     if (T < 0) return;
+    __shared__ int64_t sa[4], sb[4];
+    int64_t out = 0, stay = 0;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        if (rnd[v] == kPresent && (int64_t)deg[v] <= T) {
-            rnd[v] = r;
-            dap[v] = deg[v];
+        if (rnd[v] == kPresent) {
+            const int64_t len = off[v + 1] - off[v];
+            if ((int64_t)deg[v] <= T) {
+                rnd[v] = r;
+                dap[v] = deg[v];
+                out += len;
+            } else {
+                stay += len;
+            }
         }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        out += __shfl_down(out, o, 64);
+        stay += __shfl_down(stay, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { sa[wid] = out; sb[wid] = stay; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t to = 0, ts = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { to += sa[w]; ts += sb[w]; }
+        if (to) atomicAdd((unsigned long long *)&arcs[2 * r], (unsigned long long)to);
+        if (ts) atomicAdd((unsigned long long *)&arcs[2 * r + 1], (unsigned long long)ts);
+    }
+}
+
+// true when round r's decrement is cheaper pulled: the vertices still present have fewer
+// arcs than the vertices removed (null arcs: always push)
+__device__ __forceinline__ bool peel_pulls(const int64_t *arcs) {
+    return arcs != nullptr && arcs[1] < arcs[0];
 }
 
 // Vertices are taken by groups of 16 lanes (four per wave); a vertex removed in round r
 // lowers each neighbour still present by one, its row walked by its group when it has at
 // most kGroupRow entries, else by the whole wave after the groups' short rows.
-// act[0] < 0: nothing was present at the start of round r (the round is a no-op)
+// act[0] < 0: nothing was present at the start of round r (the round is a no-op).
+// arcs (this round's pair of arc totals, or null): the push runs unless peel_pulls says
+// the pull is cheaper.  A short row's up to four arcs per lane are loaded side by side.
 __global__ void k_peel_decrement(int64_t n, const int64_t *off, const int32_t *idx, int32_t *deg,
-                                 const int32_t *rnd, int r, const int64_t *act) {
-    if (act[0] < 0) return;
+                                 const int32_t *rnd, int r, const int64_t *act, const int64_t *arcs) {
+    if (act[0] < 0 || peel_pulls(arcs)) return;
     const int lane = threadIdx.x & 63, sl = lane & 15;
     int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
@@ -146,11 +183,15 @@ __global__ void k_peel_decrement(int64_t n, const int64_t *off, const int32_t *i
             b = off[grp];
             e = off[grp + 1];
             heavy = e - b > kGroupRow;
-            if (!heavy) {
-                for (int64_t p = b + sl; p < e; p += 16) {
-                    const int32_t u = idx[p];
-                    if (rnd[u] == kPresent) atomicSub(&deg[u], 1);
-                }
+            if (!heavy && e > b) {
+                int32_t u[4], ru[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = idx[b + sl + 16 * q < e ? b + sl + 16 * q : b];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ru[q] = rnd[u[q]];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (b + sl + 16 * q < e && ru[q] == kPresent) atomicSub(&deg[u[q]], 1);
             }
         }
         uint64_t hm = __ballot(heavy && sl == 0);
@@ -166,6 +207,58 @@ __global__ void k_peel_decrement(int64_t n, const int64_t *off, const int32_t *i
                 for (int q = 0; q < 4; ++q)
                     if (u[q] >= 0 && rnd[u[q]] == kPresent) atomicSub(&deg[u[q]], 1);
             }
+        }
+    }
+}
+
+// Pull form of round r's decrement: every vertex still present lowers its own degree by
+// the number of its neighbours removed in round r (the same degrees the push leaves).
+// Runs only when peel_pulls(arcs); short rows by groups of 16 lanes, long ones by a wave.
+__global__ void k_peel_pull(int64_t n, const int64_t *off, const int32_t *idx, int32_t *deg, const int32_t *rnd,
+                            int r, const int64_t *act, const int64_t *arcs) {
+    if (act[0] < 0 || !peel_pulls(arcs)) return;
+    const int lane = threadIdx.x & 63, sl = lane & 15;
+    int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (; grp - (lane >> 4) < n; grp += ngrp) {      // while the wave's first group has a vertex
+        int64_t b = 0, e = 0;
+        bool light = false, heavy = false;
+        if (grp < n && rnd[grp] == kPresent) {
+            b = off[grp];
+            e = off[grp + 1];
+            heavy = e - b > kGroupRow;
+            light = !heavy && e > b;
+        }
+        int32_t c = 0;
+        if (light) {
+            int32_t u[4], ru[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u[q] = idx[b + sl + 16 * q < e ? b + sl + 16 * q : b];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ru[q] = rnd[u[q]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c += (b + sl + 16 * q < e && ru[q] == r) ? 1 : 0;
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) c += __shfl_xor(c, o, 16);
+        if (light && sl == 0 && c) deg[grp] -= c;
+        uint64_t hm = __ballot(heavy && sl == 0);
+        while (hm) {
+            const int src = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const int64_t hb = __shfl(b, src, 64), he = __shfl(e, src, 64);
+            const int64_t hv = __shfl(grp, src, 64);
+            int32_t hc = 0;
+            for (int64_t p0 = hb + lane; p0 < he; p0 += 256) {     // four loads in flight per lane
+                int32_t u[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = p0 + 64 * q < he ? idx[p0 + 64 * q] : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) hc += (u[q] >= 0 && rnd[u[q]] == r) ? 1 : 0;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) hc += __shfl_xor(hc, o, 64);
+            if (lane == 0 && hc) deg[hv] -= hc;
         }
     }
 }
@@ -420,12 +513,21 @@ __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, c
             light = e - b <= kGroupRow;
             heavy = !light;
         }
-        if (light)
-            for (int64_t p = b + sl; p < e; p += 16) {
-                const int32_t r = rank[idx[p]];
-                arc_rank[p] = r;
-                c += r > rv;
+        if (light && e > b) {          // up to four arcs per lane, their loads side by side
+            int32_t u[4], ru[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u[q] = idx[b + sl + 16 * q < e ? b + sl + 16 * q : b];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ru[q] = rank[u[q]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t p = b + sl + 16 * q;
+                if (p < e) {
+                    arc_rank[p] = ru[q];
+                    c += ru[q] > rv;
+                }
             }
+        }
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) c += __shfl_xor(c, o, 16);
         if (light && sl == 0) outdeg[rv] = c;
@@ -649,6 +751,7 @@ struct OrientWs {
     uint32_t *keys, *keys_alt;
     int32_t *vals, *vals_alt;
     int64_t *rs, *thr, *outdeg;
+    int64_t *arcs;           // per round: arcs of the removed and of the remaining vertices
     int32_t *arc_rank;       // rank of each arc's head, written by the counting pass of the
                              // directing and read by the filling pass (one gather per arc)
     void *scan_ws, *radix_ws;
@@ -676,6 +779,7 @@ static size_t carve_orient(Carver &c, int64_t n, int64_t nnz, OrientWs *w, int64
     w->vals_alt = c.take<int32_t>(nn);
     w->rs = c.take<int64_t>(2 * 128);
     w->thr = c.take<int64_t>(128);
+    w->arcs = c.take<int64_t>(2 * 128);
     w->outdeg = c.take<int64_t>(nn + 1);
     w->arc_rank = c.take<int32_t>(nnz > 0 ? nnz : 1);
     w->scan_ws = c.take<char>(scan_workspace(nn + 1));
@@ -756,6 +860,7 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
     if ((rc = fill_i32(w.err, 0, 1, s))) return rc;
     if ((rc = fill_i64(w.rs, 0, 2 * 128, s))) return rc;
     if ((rc = fill_i64(w.thr, -1, 128, s))) return rc;
+    if ((rc = fill_i64(w.arcs, 0, 2 * 128, s))) return rc;
     if (stats && (rc = fill_i64(stats, 0, 2 + ARB_MAX_ROUNDS, s))) return rc;
     int32_t *dap = dap_out ? dap_out : w.dap;
     int32_t *rnd = w.rnd;
@@ -793,9 +898,11 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
             } else {
                 k_peel_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, r, w.rs);
                 k_peel_threshold<<<1, 64, 0, s>>>(r, eps, w.rs, w.thr, stats);
-                k_peel_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, w.thr);
+                k_peel_mark<<<gb, 256, 0, s>>>(n, g->offsets, w.deg, rnd, dap, r, w.thr, w.arcs);
             }
-            k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, w.thr + r);
+            const int64_t *arcs = b ? nullptr : w.arcs + 2 * r;
+            k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, w.thr + r, arcs);
+            if (!b) k_peel_pull<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, w.thr + r, arcs);
         }
     } else if (method == ARB_ORIENT_DEGREE) {
         k_all_round0<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap);
@@ -821,7 +928,7 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
             k_present_compact<<<gb, 256, 0, s>>>(n, rnd, w.deg, w.outdeg, w.keys, w.vals);
             if ((rc = radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, c, kDegBits, w.radix_ws, s))) return rc;
             k_gp_mark<<<grid_for(sr, 256, 4096), 256, 0, s>>>(sr, w.vals, w.deg, rnd, dap, r);
-            k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, act);
+            k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, act, nullptr);
             ++r;
         }
         R = r;
@@ -838,7 +945,7 @@ static int orient_impl(const arb_csr *g, double eps, int validate, arb_ocsr *out
                 k_kcore_reduce<<<gb, 256, 0, s>>>(n, w.deg, rnd, st);
                 k_kcore_threshold<<<1, 64, 0, s>>>(st, T);
                 k_kcore_mark<<<gb, 256, 0, s>>>(n, w.deg, rnd, dap, r, T);
-                k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, T);
+                k_peel_decrement<<<gw, 256, 0, s>>>(n, g->offsets, g->indices, w.deg, rnd, r, T, nullptr);
             }
             int64_t h[2] = {0, 0};
             ARB_HIP(hipMemcpyAsync(&h[0], T, sizeof(int64_t), hipMemcpyDeviceToHost, s));
