@@ -42,11 +42,20 @@ __global__ void k_feat_rows(int64_t n, const int64_t *off, const int32_t *idx, f
         }
         const bool big = e - s > 64;
         int64_t sum = 0;
-        if (!big)
-            for (int64_t p = s + sl; p < e; p += 16) {
-                const int32_t u = idx[p];
-                sum += off[u + 1] - off[u];
+        if (!big && e > s) {           // up to four entries per lane, their loads side by side
+            int32_t u[4];
+            int64_t lo[4], hi[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u[q] = idx[s + sl + 16 * q < e ? s + sl + 16 * q : s];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                lo[q] = off[u[q]];
+                hi[q] = off[u[q] + 1];
             }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (s + sl + 16 * q < e) sum += hi[q] - lo[q];
+        }
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
         uint64_t m = __ballot(big && sl == 0);

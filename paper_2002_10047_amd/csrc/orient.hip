@@ -558,12 +558,12 @@ __global__ void k_dir_count(int64_t n, const int64_t *off, const int32_t *idx, c
     }
 }
 
-// Write the higher-ranked neighbours' ranks into the row of the vertex's rank (order of
-// the input row; sorted afterwards).
+// Write the higher-ranked neighbours' ranks into the row of the vertex's rank: sorted for
+// input rows of at most kGroupRow entries, in the input row's order for longer ones
+// (sorted afterwards).
 __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *arc_rank, const int32_t *rank,
                            const int64_t *ooff, int32_t *oidx) {
-    const int lane = threadIdx.x & 63, sl = lane & 15, gsh = lane & 48;
-    const uint32_t below16 = (1u << sl) - 1u;
+    const int lane = threadIdx.x & 63, sl = lane & 15;
     const uint64_t below = lanes_below_mask();
     int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
@@ -578,7 +578,10 @@ __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *arc_ran
             w = ooff[rv];
             heavy = len > kGroupRow;
         }
-        // short rows: the wave steps until its longest one is done (at most 4 steps)
+        // short rows (at most four entries per lane): each kept entry goes straight to its
+        // sorted place, the number of the row's kept entries below it (entries are
+        // distinct ranks; a dropped entry reads as INT32_MAX and counts for none).  The
+        // wave takes as many of the four slots as its longest short row needs
         const int64_t ll = heavy ? 0 : len;
         int64_t lmax = ll;
 #pragma unroll
@@ -586,14 +589,27 @@ __global__ void k_dir_fill(int64_t n, const int64_t *off, const int32_t *arc_ran
             const int64_t y = __shfl_xor(lmax, o, 64);
             lmax = y > lmax ? y : lmax;
         }
-        int64_t wl = w;
-        for (int64_t q = 0; q < lmax; q += 16) {
-            const int32_t ru = (q + sl < ll) ? arc_rank[b + q + sl] : -1;
-            const bool keep = ru > rv;
-            const uint32_t m = (uint32_t)(__ballot(keep) >> gsh) & 0xffffu;
-            if (keep) oidx[wl + __popc(m & below16)] = ru;
-            wl += __popc(m);
+        int32_t v[4];
+        int pos[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t ru = (16 * q + sl < ll) ? arc_rank[b + 16 * q + sl] : -1;
+            v[q] = ru > rv ? ru : INT32_MAX;
+            pos[q] = 0;
         }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            if (16 * qq >= lmax) break;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int32_t y = __shfl(v[qq], j, 16);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pos[q] += y < v[q] ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v[q] != INT32_MAX) oidx[w + pos[q]] = v[q];
         uint64_t hm = __ballot(heavy && sl == 0);
         while (hm) {
             const int src = __ffsll((unsigned long long)hm) - 1;
@@ -624,7 +640,7 @@ constexpr int kMidRow = 2048;
 
 // Rows of at most 16 entries: one group of 16 lanes per row, each lane's destination is
 // the number of smaller entries (entries are distinct); rows of 17..64 entries: the same
-// by the whole wave after its groups' short rows.  Longer rows are listed for the kernels
+// by the whole wave after its groups' short rows, unless the row is already sorted.  Longer rows are listed for the kernels
 // below (mid: 65..kMidRow entries, big: longer; cnt[0], cnt[1] entries), with one global
 // atomic per block and round.  Also reduces the largest row length.
 __global__ void __launch_bounds__(256) k_row_sort_small(int64_t n, const int64_t *ooff, int32_t *oidx,
@@ -663,6 +679,8 @@ __global__ void __launch_bounds__(256) k_row_sort_small(int64_t n, const int64_t
             const int64_t ws = __shfl(s, src, 64);
             const int wd = __shfl(d, src, 64);
             const int32_t y = lane < wd ? oidx[ws + lane] : 0x7fffffff;
+            const int32_t ynext = __shfl_down(y, 1, 64);
+            if (__ballot(lane + 1 < wd && ynext < y) == 0) continue;     // sorted by the fill
             int wpos = 0;
             for (int j = 0; j < wd; ++j) wpos += __shfl(y, j, 64) < y;
             if (lane < wd) oidx[ws + wpos] = y;
