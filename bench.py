@@ -393,7 +393,9 @@ class Workload:
         arb = self.arb
         oo = arb.arb_orient(self.off, self.idx, eps=self.eps) if orient else self.o
         if sname == "learned":
-            f = arb.arb_features(oo["ooff"], oo["oidx"], oo["round"], oo["rank"]) if orient else self.feat
+            # the schedule reads the cost of roots above the 64-tier only
+            f = (arb.arb_features_min_degree(oo["ooff"], oo["oidx"], oo["round"], oo["rank"],
+                                             arb.ARB_LEARNED_MIN_DEGREE) if orient else self.feat)
             for k in self.ks:
                 self.opts[sname][k].features = f.data_ptr()
                 self.opts[sname][k]._keep = (self.weights[k], f)

@@ -369,6 +369,16 @@ int arb_peel(const arb_ocsr *dg, int k, double *best_density, int64_t *rounds, i
 int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank,
                  float *feat, void *stream);
 
+/* The rows of arb_features for the roots with at least min_degree out-neighbours only;
+ * the other rows of feat are left as they were (min_degree = 0: every row, the same as
+ * arb_features).  The learned schedule reads the cost of roots with at least
+ * ARB_LEARNED_MIN_DEGREE out-neighbours only (the smaller roots share the 64-tier, where
+ * the order of the light roots does not matter), so features computed with that bound
+ * give it all it reads.  ARB_EINVAL on a negative min_degree or the arb_features errors. */
+#define ARB_LEARNED_MIN_DEGREE 65
+int arb_features_min_degree(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank,
+                            int64_t min_degree, float *feat, void *stream);
+
 /* y[r] = MLP(x[r]) for rows r < rows; x float[rows][3]; weights bf16 (ARB_MLP_PARAMS,
  * layout W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[1][64] b4[1]);
  * act (nullable) float[rows][192] receives the three hidden pre-activations for

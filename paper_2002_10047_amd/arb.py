@@ -36,6 +36,7 @@ ARB_MAX_K = _define("ARB_MAX_K") or 10
 ARB_MAX_LOCAL = _define("ARB_MAX_LOCAL") or 768
 ARB_MAX_ROUNDS = _define("ARB_MAX_ROUNDS") or 64
 ARB_MLP_PARAMS = _define("ARB_MLP_PARAMS") or 8641
+ARB_LEARNED_MIN_DEGREE = _define("ARB_LEARNED_MIN_DEGREE") or 65
 ARB_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -92,6 +93,7 @@ _sigs = {
     "arb_count_noalloc": ([P, I32, P, P, P, P], I32),
     "arb_count_instrumented": ([P, I32, P, P, P, P, SZ, P], I32),
     "arb_features": ([P, P, P, P, P], I32),
+    "arb_features_min_degree": ([P, P, P, I64, P, P], I32),
     "arb_mlp_forward": ([P, P, I64, P, P, P], I32),
     "arb_mlp_workspace": ([I64], SZ),
     "arb_mlp_backward": ([P, P, P, P, I64, P, P, SZ, P], I32),
@@ -516,13 +518,34 @@ def arb_segment_sum_u64(values, offsets, stream=None):
 
 # ------------------------------------------------------------------ learned schedule
 
-def arb_features(ooff, oidx, round_orig=None, rank=None, stream=None):
+def _features_out(ooff, out):
     n = ooff.numel() - 1
-    feat = torch.empty(max(n, 1) * 3, dtype=torch.float32, device=ooff.device)
+    if out is None:
+        return torch.empty(max(n, 1) * 3, dtype=torch.float32, device=ooff.device)
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < max(n, 1) * 3:
+        raise ValueError("out must be a contiguous float32 tensor of at least 3n elements")
+    return out
+
+
+def arb_features(ooff, oidx, round_orig=None, rank=None, stream=None, out=None):
+    """Per-root features [n, 3]; out: optional float32 device tensor of at least 3n elements."""
+    n = ooff.numel() - 1
+    feat = _features_out(ooff, out)
     dg = _ocsr(ooff, oidx)
     _check(_lib.arb_features(ctypes.byref(dg), _ptr(round_orig), _ptr(rank), _ptr(feat), _stream(stream)),
            "arb_features")
-    return feat[: 3 * n].view(n, 3)
+    return feat.view(-1)[: 3 * n].view(n, 3)
+
+
+def arb_features_min_degree(ooff, oidx, round_orig, rank, min_degree, stream=None, out=None):
+    """The rows of arb_features for roots with at least min_degree out-neighbours; the other
+    rows keep what `out` held (uninitialised without `out`)."""
+    n = ooff.numel() - 1
+    feat = _features_out(ooff, out)
+    dg = _ocsr(ooff, oidx)
+    _check(_lib.arb_features_min_degree(ctypes.byref(dg), _ptr(round_orig), _ptr(rank), int(min_degree),
+                                        _ptr(feat), _stream(stream)), "arb_features_min_degree")
+    return feat.view(-1)[: 3 * n].view(n, 3)
 
 
 def arb_mlp_forward(w_bf16, x, want_act=False, stream=None):

@@ -30,15 +30,19 @@ __device__ __forceinline__ void load_weights(const uint16_t *wb, float *W) {
 
 // A group of 16 lanes per row (four per wave); rows with more than 64 out-neighbours are
 // summed by the whole wave after its groups' rows, four loads in flight per lane.
-__global__ void k_feat_rows(int64_t n, const int64_t *off, const int32_t *idx, float *feat) {
+// Rows with fewer than dmin entries are skipped (their features are left as they were).
+__global__ void k_feat_rows(int64_t n, const int64_t *off, const int32_t *idx, float *feat, int64_t dmin) {
     const int lane = threadIdx.x & 63, sl = lane & 15;
     int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
     for (; r - (lane >> 4) < n; r += ngrp) {          // while the wave's first group has a row
         int64_t s = 0, e = 0;
+        bool on = false;
         if (r < n) {
             s = off[r];
             e = off[r + 1];
+            on = e - s >= dmin;
+            if (!on) e = s;
         }
         const bool big = e - s > 64;
         int64_t sum = 0;
@@ -76,16 +80,20 @@ __global__ void k_feat_rows(int64_t n, const int64_t *off, const int32_t *idx, f
             for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
             if ((lane >> 4) == (src >> 4)) sum = part;
         }
-        if (r < n && sl == 0) {
+        if (on && sl == 0) {
             feat[3 * r + 0] = log2f(1.0f + (float)(e - s));
             feat[3 * r + 1] = log2f(1.0f + (float)sum);
         }
     }
 }
 
-__global__ void k_feat_round(int64_t n, const int32_t *round_orig, const int32_t *rank, float *feat) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        feat[3 * (int64_t)rank[v] + 2] = round_orig ? (float)round_orig[v] : 0.f;
+__global__ void k_feat_round(int64_t n, const int32_t *round_orig, const int32_t *rank, float *feat,
+                             const int64_t *off, int64_t dmin) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rv = rank[v];
+        if (dmin > 0 && off[rv + 1] - off[rv] < dmin) continue;
+        feat[3 * rv + 2] = round_orig ? (float)round_orig[v] : 0.f;
+    }
 }
 
 // ------------------------------------------------------------------ forward
@@ -400,22 +408,30 @@ int learned_cost(const arb_ocsr *dg, int k, const uint16_t *w, const float *feat
 
 using namespace arb;
 
-extern "C" int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank, float *feat,
-                            void *stream) {
+extern "C" int arb_features_min_degree(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank,
+                                       int64_t min_degree, float *feat, void *stream) {
     hipStream_t s = as_stream(stream);
-    if (!dg || !feat || dg->n < 0 || !dg->offsets || (dg->m > 0 && !dg->indices) || (round_orig && !rank)) {
+    if (!dg || !feat || dg->n < 0 || !dg->offsets || (dg->m > 0 && !dg->indices) || (round_orig && !rank) ||
+        min_degree < 0) {
         set_error(ARB_EINVAL);
         return ARB_EINVAL;
     }
     const int64_t n = dg->n;
     if (n > 0) {
-        k_feat_rows<<<grid_for(n * 16, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, feat);
-        if (rank) k_feat_round<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, round_orig, rank, feat);
-        else k_feat_round<<<1, 64, 0, s>>>(0, nullptr, nullptr, feat);
+        k_feat_rows<<<grid_for(n * 16, 256, 8192), 256, 0, s>>>(n, dg->offsets, dg->indices, feat, min_degree);
+        if (rank)
+            k_feat_round<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, round_orig, rank, feat, dg->offsets, min_degree);
+        else
+            k_feat_round<<<1, 64, 0, s>>>(0, nullptr, nullptr, feat, nullptr, 0);
         if (hipGetLastError() != hipSuccess) { set_error(ARB_EHIP); return ARB_EHIP; }
     }
     set_error(ARB_OK);
     return ARB_OK;
+}
+
+extern "C" int arb_features(const arb_ocsr *dg, const int32_t *round_orig, const int32_t *rank, float *feat,
+                            void *stream) {
+    return arb_features_min_degree(dg, round_orig, rank, 0, feat, stream);
 }
 
 extern "C" int arb_mlp_forward(const uint16_t *w_bf16, const float *x, int64_t rows, float *y, float *act,

@@ -48,6 +48,15 @@ def test_features_per_root_and_work(arb, orc, gi):
     assert np.allclose(f[:, 0], np.log2(1 + fr[:, 0]), rtol=1e-5, atol=1e-5)
     assert np.allclose(f[:, 1], np.log2(1 + fr[:, 1]), rtol=1e-5, atol=1e-5)
     assert np.array_equal(f[:, 2], fr[:, 2])
+    # rows of roots below a degree bound are left as they were, the others are the same
+    d_all = np.diff(o["ooff"].cpu().numpy())
+    for dm in (1, 8, int(arb.ARB_LEARNED_MIN_DEGREE)):
+        say("features min_degree", g.name, dm)
+        buf = torch.full((3 * n,), float("nan"), dtype=torch.float32, device="cuda")
+        fb = arb.arb_features_min_degree(o["ooff"], o["oidx"], o["round"], o["rank"], dm, out=buf).cpu().numpy()
+        on = d_all >= dm
+        assert np.array_equal(fb[on], f[on])
+        assert np.isnan(fb[~on]).all()
     lc = orc.local_cliques(n, ref["ooff"], ref["oidx"], 6)
     d = np.diff(ref["ooff"])
     rows = np.repeat(np.arange(n), d)
