@@ -396,16 +396,21 @@ __device__ __forceinline__ Acc dfs64(AS3<Lds> *T, uint64_t J) {
             const int z2 = two ? __builtin_ctzll(R) : z1;
             R &= R - 1;
             const uint64_t r1 = row64(T, z1), r2 = row64(T, z2);
-            leaf += (unsigned)__popcll(above1 & r1) + (unsigned)__popcll(R & r2);   // R = 0 unless two
             if constexpr (PV) {
-                // each member belongs to as many of the node's cliques as it has neighbours in J
+                // each member belongs to as many of the node's cliques as it has neighbours
+                // in J (the rows are symmetric), and the node's cliques, the edges of J, are
+                // half the sum of those: no separate count of the neighbours above
                 const unsigned a1 = (unsigned)__popcll(J & r1);
                 if (a1) lds_add(&T->cnt[z1], (unsigned long long)a1);
                 const unsigned a2 = two ? (unsigned)__popcll(J & r2) : 0u;
                 if (a2) lds_add(&T->cnt[z2], (unsigned long long)a2);
+                leaf += a1 + a2;
+                (void)above1;
+            } else {
+                leaf += (unsigned)__popcll(above1 & r1) + (unsigned)__popcll(R & r2);   // R = 0 unless two
             }
         }
-        out.c += leaf;
+        out.c += PV ? leaf >> 1 : leaf;
     } else {
         while (R) {
             const int z = __builtin_ctzll(R);
@@ -490,15 +495,13 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
         uint32_t rz[W];
         load_row<W, 0, Lds>(T, z, rz);
         if constexpr (L == 2) {
-            unsigned a = 0, c = 0;
+            // per-vertex leaf level (symmetric rows): z's neighbours in J are its credit, and
+            // the node's count, the edges of J, is half the sum of the credits
+            unsigned a = 0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                uint32_t t = J.w[w] & rz[w];
-                a += __popc(t);
-                c += __popc(t & gtmask(z, w));
-            }
+            for (int w = 0; w < W; ++w) a += __popc(J.w[w] & rz[w]);
             if (a) lds_add(&T->cnt[z], (unsigned long long)a);
-            out.c += c;
+            out.c += a;
         } else {
             Bits<W> K;
 #pragma unroll
@@ -513,6 +516,7 @@ __device__ __attribute__((always_inline)) inline Acc dfs_inline(AS3<Lds> *T, con
             out.nodes += sub.nodes;
         }
     }
+    if constexpr (L == 2) out.c >>= 1;      // every edge of J was counted from both ends
     return out;
 }
 
