@@ -32,7 +32,7 @@ def _define(name):
     return int(m.group(1)) if m else None
 
 
-ARB_MAX_K = _define("ARB_MAX_K") or 10
+ARB_MAX_K = _define("ARB_MAX_K") or 32
 ARB_MAX_LOCAL = _define("ARB_MAX_LOCAL") or 768
 ARB_MAX_ROUNDS = _define("ARB_MAX_ROUNDS") or 64
 ARB_MLP_PARAMS = _define("ARB_MLP_PARAMS") or 8641
