@@ -116,8 +116,9 @@ COUNT_GRAPHS = [
     ("rmat14", lambda: gg.rmat(14, 200000, seed=9), range(3, 7)),
     ("rgg2d", lambda: gg.rgg(20000, 2, 20.0, 5), range(3, 9)),
     ("gnp1000", lambda: gg.gnp(1000, 0.4, 3), range(3, 5)),
-    # out-degrees spread over every tier up to ~600 with few cliques (mostly bipartite edges)
-    ("sbm1500", lambda: gg.sbm2(1500, 0.05, 0.8, 7), range(3, 7)),
+    # out-degrees spread over every tier up to ~600 with few cliques (mostly bipartite edges):
+    # per-vertex counts of every LDS tier at recursion depths up to 5
+    ("sbm1500", lambda: gg.sbm2(1500, 0.05, 0.8, 7), range(3, 9)),
     # 279 roots with 769..865 out-neighbours: the big-root path (bit rows in global scratch)
     ("sbm2000", lambda: gg.sbm2(2000, 0.05, 0.85, 11), range(3, 5)),
 ]
