@@ -262,6 +262,9 @@ def test_pair_items_overflow_lds(arb, orc):
     ("c1", lambda: gg.config_graph("c1"), (11, 14, 29, 30)),
     ("gnp150", lambda: gg.gnp(150, 0.5, 1), (9, 10, 11, 12)),
     ("T(39,13)", lambda: gg.turan(39, 13), (11, 13, 14)),
+    # a planted K24 whose lowest-ranked member has 82 out-neighbours: that 128-tier root
+    # counts every deep clique through it (8855 of the 10626 at k = 20)
+    ("er600_K24", lambda: gg.er_planted(600, 40000, 24, 3), (9, 10, 11, 14, 20)),
 ])
 def test_deep_k(arb, orc, name, mk, ks):
     # k > 10: the walk below the seventh level keeps its frames in private memory
