@@ -265,6 +265,8 @@ def test_pair_items_overflow_lds(arb, orc):
     # a planted K24 whose lowest-ranked member has 82 out-neighbours: that 128-tier root
     # counts every deep clique through it (8855 of the 10626 at k = 20)
     ("er600_K24", lambda: gg.er_planted(600, 40000, 24, 3), (9, 10, 11, 14, 20)),
+    # the same in the 256-tier: the K16's lowest-ranked member has 134 out-neighbours
+    ("er700_K16", lambda: gg.er_planted(700, 60000, 16, 7), (9, 10, 11, 13, 16)),
 ])
 def test_deep_k(arb, orc, name, mk, ks):
     # k > 10: the walk below the seventh level keeps its frames in private memory
