@@ -267,6 +267,10 @@ def test_pair_items_overflow_lds(arb, orc):
     ("er600_K24", lambda: gg.er_planted(600, 40000, 24, 3), (9, 10, 11, 14, 20)),
     # the same in the 256-tier: the K16's lowest-ranked member has 134 out-neighbours
     ("er700_K16", lambda: gg.er_planted(700, 60000, 16, 7), (9, 10, 11, 13, 16)),
+    # the 384-tier (lowest-ranked members of the K14: 293, 298 out-neighbours) and the
+    # 512-tier (of the K13: 385)
+    ("er1500_K14", lambda: gg.er_planted(1500, 250000, 14, 5), (10, 11, 14)),
+    ("er2000_K13", lambda: gg.er_planted(2000, 450000, 13, 3), (11, 13)),
 ])
 def test_deep_k(arb, orc, name, mk, ks):
     # k > 10: the walk below the seventh level keeps its frames in private memory
