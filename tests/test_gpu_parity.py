@@ -271,6 +271,8 @@ def test_pair_items_overflow_lds(arb, orc):
     # 512-tier (of the K13: 385)
     ("er1500_K14", lambda: gg.er_planted(1500, 250000, 14, 5), (10, 11, 14)),
     ("er2000_K13", lambda: gg.er_planted(2000, 450000, 13, 3), (11, 13)),
+    # the 768-tier (the K12's lowest-ranked member: 547 out-neighbours)
+    ("er2600_K12", lambda: gg.er_planted(2600, 800000, 12, 4), (12,)),
 ])
 def test_deep_k(arb, orc, name, mk, ks):
     # k > 10: the walk below the seventh level keeps its frames in private memory
