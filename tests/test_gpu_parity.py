@@ -257,6 +257,23 @@ def test_pair_items_overflow_lds(arb, orc):
             assert np.all(pv == esym([800] * 2, k - 1)), (k, big)
 
 
+def _sbm2000_with_k12():
+    # sbm2000 plus a K12 on its 12 largest out-degree roots (tests/golden/pair_items.json's
+    # graph): the clique's lowest-ranked member has 862 out-neighbours, so the deep walk
+    # runs in the global-scratch kernel
+    base = gg.sbm2(2000, 0.05, 0.85, 11)
+    off, idx = np.asarray(base.offsets), np.asarray(base.indices)
+    u = np.repeat(np.arange(base.n), np.diff(off))
+    keep = u < idx
+    deg = np.diff(off)
+    # the largest out-degrees under the peel at eps = 1 are the vertices of least degree
+    # in the denser half; take them by (degree, id) as the peel orders them
+    mem = np.sort(np.lexsort((np.arange(base.n), deg))[:12])
+    ia, ib = np.triu_indices(12, 1)
+    return gg.csr_from_pairs(base.n, np.concatenate([u[keep], mem[ia]]), np.concatenate([idx[keep], mem[ib]]),
+                             "sbm2000+K12")
+
+
 @pytest.mark.parametrize("name,mk,ks", [
     ("K34", lambda: gg.complete(34), (11, 30, 31, 32)),
     ("c1", lambda: gg.config_graph("c1"), (11, 14, 29, 30)),
@@ -273,6 +290,7 @@ def test_pair_items_overflow_lds(arb, orc):
     ("er2000_K13", lambda: gg.er_planted(2000, 450000, 13, 3), (11, 13)),
     # the 768-tier (the K12's lowest-ranked member: 547 out-neighbours)
     ("er2600_K12", lambda: gg.er_planted(2600, 800000, 12, 4), (12,)),
+    ("sbm2000_K12", _sbm2000_with_k12, (12,)),
 ])
 def test_deep_k(arb, orc, name, mk, ks):
     # k > 10: the walk below the seventh level keeps its frames in private memory
