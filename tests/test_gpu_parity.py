@@ -306,6 +306,19 @@ def test_deep_k(arb, orc, name, mk, ks):
             assert t == math.comb(34, k) and np.all(pv == math.comb(33, k - 1))
 
 
+def test_pair_items_deep_k(arb, orc):
+    # the K12 planted on the SBM graph's largest roots with big_max_degree = 768: every root
+    # above 768 out-neighbours becomes one (root, child) item per out-neighbour, counted in
+    # the LDS tiers, so the clique's 12-clique is found by a pair item's deep walk
+    g = _sbm2000_with_k12()
+    o = gpu_orient(arb, g, 1.0)
+    say("sbm2000_K12 pair items k 12")
+    t_ref, pv_ref = orc.count(g, 12, per_vertex=True, nthreads=8)
+    assert t_ref == 1
+    t, pv = gpu_count(arb, o, 12, per_vertex=True, big_max_degree=768)
+    assert t == t_ref and np.array_equal(pv, pv_ref)
+
+
 def test_c1_plain_schedule(arb, orc):
     # the small benchmark graph with the plain (one launch per tier, one team per root)
     # schedule, totals and per-vertex counts
