@@ -274,7 +274,7 @@ def _sbm2000_with_k12():
                              "sbm2000+K12")
 
 
-@pytest.mark.parametrize("name,mk,ks", [
+DEEP_K_GRAPHS = [
     ("K34", lambda: gg.complete(34), (11, 30, 31, 32)),
     ("c1", lambda: gg.config_graph("c1"), (11, 14, 29, 30)),
     ("gnp150", lambda: gg.gnp(150, 0.5, 1), (9, 10, 11, 12)),
@@ -291,7 +291,10 @@ def _sbm2000_with_k12():
     # the 768-tier (the K12's lowest-ranked member: 547 out-neighbours)
     ("er2600_K12", lambda: gg.er_planted(2600, 800000, 12, 4), (12,)),
     ("sbm2000_K12", _sbm2000_with_k12, (12,)),
-])
+]
+
+
+@pytest.mark.parametrize("name,mk,ks", DEEP_K_GRAPHS)
 def test_deep_k(arb, orc, name, mk, ks):
     # k > 10: the walk below the seventh level keeps its frames in private memory
     g = mk()
