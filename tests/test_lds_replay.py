@@ -57,7 +57,8 @@ def test_turan90_k8_in_bounds(replay, orc):
 
 
 @pytest.mark.parametrize("mk,ks", [(lambda: gg.gnp(150, 0.5, 1), (5, 8)), (lambda: gg.complete(40), (6, 8)),
-                                   (lambda: gg.turan(70, 7), (6, 8)), (lambda: gg.config_graph("c1"), (4, 8))])
+                                   (lambda: gg.turan(70, 7), (6, 8)), (lambda: gg.config_graph("c1"), (4, 8)),
+                                   (lambda: gg.gnp(400, 0.3, 2), (7, 8))])
 def test_replay_matches_oracle(replay, orc, mk, ks):
     g = mk()
     o = orc.orient(g, 1.0)
